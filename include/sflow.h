@@ -1,0 +1,171 @@
+/*
+ * sflow.h - C ABI of the structure-flow predictor-update filter for AMD MI355X (gfx950).
+ *
+ * The filter estimates structure flow, the scene's 3-D velocity relative to the camera at
+ * every pixel divided by its range (Adarve & Mahony, "Real-time Structure Flow",
+ * arXiv 2406.18031, Section "Structure Flow", eq:homogeneous_flow; units rad/s), from a
+ * stream of brightness images Y and inverse-depth maps rho (eq:inv_depth, reference range
+ * 1 m).  Each frame runs the pyramidal predictor-update filter of Section "Filter
+ * Architecture": an upwind finite-difference prediction of the previous flow and inverse
+ * depth (Section "Numerical prediction"), then a per-pixel least-squares update from the
+ * new image and depth (Section "State update"), smoothing and coarse-to-fine
+ * reconstruction (eq:hflow_reconstruction).
+ *
+ * Conventions shared by every call
+ *  - Images are on a pinhole grid: pixel (i, j) (row i, column j) looks along
+ *    normalize(((j - cx)/fx, (i - cy)/fy, 1)) with x right, y down, z forward.
+ *  - Image arguments are caller-owned DEVICE pointers (HIP memory, e.g. torch tensors),
+ *    rows x cols, row-major, contiguous.  Element type is float32, or float16 when the
+ *    context was created with storage = SF_FP16.  Host pointers are rejected.
+ *  - All device work is enqueued on the HIP stream given to sf_create, in stream order, like
+ *    hipMemcpyAsync: the caller must not modify an input until that stream has passed the
+ *    call that consumed it.  Calls return without waiting for the device, except
+ *    sf_get_state / sf_set_state, which synchronise the stream.
+ *  - Every call validates all arguments before it enqueues anything: a call that returns an
+ *    error leaves the context unchanged (except the sticky SF_ERR_HIP below).
+ *  - A context may be used from one host thread at a time.
+ *  - Return values are sf_status codes; nothing throws or aborts across the ABI.
+ *    sf_last_error(ctx) gives a text for the last failure on that context.
+ *  - A HIP failure (launch error, fault reported by the runtime) makes the context
+ *    unusable: it and every later call return SF_ERR_HIP; destroy it.
+ */
+#ifndef SFLOW_H
+#define SFLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sf_ctx_s* sf_ctx;
+
+typedef enum {
+    SF_OK = 0,
+    SF_ERR_INVALID_ARG = -1, /* NULL/host pointer, bad size, dt <= 0 or not finite, ...     */
+    SF_ERR_STATE = -2,       /* call not valid now (push before sf_set_camera, get before push) */
+    SF_ERR_OOM = -3,         /* device allocation failed                                   */
+    SF_ERR_HIP = -4,         /* a HIP runtime call failed; the context is unusable          */
+    SF_ERR_UNSUPPORTED = -5, /* valid request this build does not implement                */
+    SF_ERR_NUMERIC = -6      /* reserved                                                   */
+} sf_status;
+
+/* element type of images and stored state */
+enum { SF_FP32 = 0, SF_FP16 = 1 };
+/* update stage: the paper's least-squares update, or the learned correction */
+enum { SF_UPDATE_PLAIN = 0, SF_UPDATE_LEARNED = 1 };
+
+/* Readings of points the paper leaves ambiguous (bit flags; 0 = the default readings):
+ *  SF_READ_DOMINANT_LITERAL  dominant optical flow as printed in Section "Numerical
+ *                            prediction" (picks the neighbour of smaller magnitude); the
+ *                            default follows the text (the larger one).
+ *  SF_READ_SOURCE_LITERAL    the source term f<eta,w> with the full step in both the column
+ *                            and the row half-step, as printed; the default applies half of it
+ *                            in each, matching eq:hflow_propagation_discrete.
+ *  SF_READ_NO_CFL_CLAMP      do not clamp the dominant flow to the stability bound of
+ *                            eq:numerical_stability (|u_hat| <= N). */
+enum {
+    SF_READ_DOMINANT_LITERAL = 1u,
+    SF_READ_SOURCE_LITERAL = 2u,
+    SF_READ_NO_CFL_CLAMP = 4u
+};
+
+/* sf_get_flow kinds (finest level).  Output is always float32, planar: component-major
+ * [components][rows][cols], contiguous. */
+enum {
+    SF_FLOW_W_RAD_S = 0,    /* 3 planes: structure flow w in rad/s (eq:homogeneous_flow)      */
+    SF_FLOW_TANGENT_PX = 1, /* 2 planes: B^T P w / dmu in pixels per frame (eq:tangent_flow)   */
+    SF_FLOW_NORMAL_PX = 2,  /* 1 plane : <eta, w> / dmu in pixels per frame (eq:normal_flow)   */
+    SF_FLOW_RHO = 3,        /* 1 plane : filtered inverse depth, 1/m                          */
+    SF_FLOW_W_FRAME = 4     /* 3 planes: structure flow in rad/frame (the filter's own unit)  */
+};
+
+#define SF_MAX_LEVELS 8
+
+typedef struct {
+    int32_t rows, cols;   /* finest grid, >= 2 each                                           */
+    int32_t levels;       /* pyramid levels H in [1, SF_MAX_LEVELS] (Section "Filter
+                             Architecture"); level h has ceil(rows/2^(h-1)) x ceil(cols/2^(h-1))
+                             pixels and every level must be at least 2 x 2                      */
+    float max_flow_px;    /* largest expected image motion per frame at the finest level, >= 0.
+                             Level h integrates N_h = max(1, ceil(max_flow_px / 2^(h-1))) steps
+                             (eq:numerical_stability)                                          */
+    int32_t smooth_iters[SF_MAX_LEVELS]; /* 5x5 averaging passes after each level's solve,
+                             finest first, in [0, 16]                                          */
+    float alpha[5];       /* weights alpha_1..alpha_5 of the image, depth, temporal, depth
+                             measurement and depth prior terms (eq:cost_top, eq:cost_invdepth);
+                             gamma_1,2 = alpha_1,2 / dmu0^2 with dmu0 = 1/sqrt(fx_h^2 + 1) the
+                             level's on-axis pixel spacing, gamma_3,4,5 = alpha_3,4,5.
+                             All five zero selects the defaults {300, 1000, 1, 1, 1}.
+                             Otherwise each must be finite and >= 0, with alpha_3 > 0 and
+                             alpha_4 + alpha_5 > 0.                                           */
+    int32_t storage;      /* SF_FP32 or SF_FP16 (images and state stored in half precision,
+                             all arithmetic in float32)                                        */
+    int32_t update;       /* SF_UPDATE_PLAIN (SF_UPDATE_LEARNED needs sf_set_weights)          */
+    uint32_t read_flags;  /* SF_READ_* bits                                                    */
+} sf_config;
+
+typedef struct {
+    double fx, fy, cx, cy; /* pinhole intrinsics of the finest level, in pixels; fx, fy > 0   */
+} sf_camera;
+
+/* Create a filter context.  Allocates all device memory for the state (double-buffered),
+ * the pyramid and work buffers.  hip_stream is a hipStream_t (NULL = default stream).
+ * On success *out owns the context until sf_destroy. */
+sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out);
+
+/* Set the camera (Section "Spherical image data structure": the grid of unit directions,
+ * its tangent bases and pixel spacing are derived from the intrinsics).  Resets the filter:
+ * the next push is a first frame. */
+sf_status sf_set_camera(sf_ctx ctx, const sf_camera* cam);
+
+/* Push frame k+1: Y brightness (any float scale), rho inverse depth in 1/m (NaN = no
+ * measurement, 0 = infinitely far, valid), dt seconds since the previous frame (> 0,
+ * finite; ignored on the first frame).  The first frame after sf_set_camera initialises the
+ * state (flow 0, inverse depth from rho with 0 where missing; Section "Ground truth
+ * evaluation").  Later frames run prediction, update, smoothing and reconstruction. */
+sf_status sf_push_frame(sf_ctx ctx, const void* Y, const void* rho, double dt);
+
+/* Write the finest-level result of the last push to out (device, float32, see SF_FLOW_*).
+ * SF_ERR_STATE before the first push; zeros after only the first push. */
+sf_status sf_get_flow(sf_ctx ctx, int32_t kind, void* out);
+
+/* Bytes of the state blob of sf_get_state / sf_set_state. */
+sf_status sf_state_size(sf_ctx ctx, size_t* bytes);
+
+/* Copy the whole filter state to / from HOST memory (synchronises the stream).  The blob is
+ * a 32-byte header {uint32 magic 'SFST', uint32 version 1, int32 levels, int32 initialised,
+ * double dt_prev, int64 frames} followed, for h = 1..H, by float32 planes of
+ * rows_h x cols_h: w (3, rad/frame), dw (3, levels below the top only), rho, Yhat.
+ * Used to resume a stream and to inject a state for single-frame checks.  sf_set_state
+ * needs a camera to be set and a blob of exactly sf_state_size bytes for this
+ * configuration. */
+sf_status sf_get_state(sf_ctx ctx, void* host_blob, size_t bytes);
+sf_status sf_set_state(sf_ctx ctx, const void* host_blob, size_t bytes);
+
+/* Release the context and all its device memory (synchronises the stream first).
+ * sf_destroy(NULL) is a no-op returning SF_OK. */
+sf_status sf_destroy(sf_ctx ctx);
+
+/* Text of the last error on ctx (or of the last failed sf_create when ctx is NULL).  The
+ * pointer stays valid until the next call on the same context. */
+const char* sf_last_error(sf_ctx ctx);
+
+/* Tile shape of the fused level kernel for level h (1-based): output tiles of tw x th
+ * pixels; tw + 2*halo_h and th + 2*halo_h must not exceed 64, where halo_h =
+ * max(N_h, 2) + 2 * smooth_iters[h-1].  0, 0 restores the built-in choice.  For tuning. */
+sf_status sf_set_tile(sf_ctx ctx, int32_t level, int32_t tw, int32_t th);
+
+/* Kernel timing for measurement.  When enabled, every push records HIP events around each
+ * kernel on the context stream; sf_kernel_times returns, per kernel kind (0 pyramid,
+ * 1 level step, 2 reconstruction), the total milliseconds and launch counts since the
+ * last reset (synchronises the stream). */
+sf_status sf_set_timing(sf_ctx ctx, int32_t enable);
+sf_status sf_kernel_times(sf_ctx ctx, double* ms3, int64_t* launches3, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFLOW_H */

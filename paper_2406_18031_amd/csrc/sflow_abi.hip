@@ -1,0 +1,641 @@
+// Host runtime and C ABI of the structure-flow filter (see include/sflow.h).
+//
+// A context owns one device arena holding, per pyramid level, the double-buffered state
+// planes (w, dw, rho, Yhat) and the pyramid's image and inverse-depth planes, all row-major
+// with rows padded to 256 bytes, plus the per-level parameter table the kernels read.  A
+// frame is: pyramid (one launch per level below the finest), one fused level-step launch
+// covering every tile of every level (levels are independent within a frame), then the
+// coarse-to-fine reconstruction (one launch per lower level).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sflow_internal.h"
+
+using namespace sflow;
+
+struct sf_ctx_s {
+    sf_config cfg{};
+    hipStream_t stream = nullptr;
+    int H = 0;
+    int esize = 4;                 // bytes per stored element
+    bool camera = false;
+    bool hip_failed = false;
+    int64_t frames = 0;            // frames pushed since the camera was set
+    int parity = 0;                // state[parity] holds the latest frame
+    double dt_prev = 0.0;
+    double cam[4] = {0, 0, 0, 0};
+    std::string err;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    LevelDev lv[kMaxLevels]{};
+    LevelDev* lv_dev = nullptr;
+    int user_tw[kMaxLevels]{};
+    int user_th[kMaxLevels]{};
+    int nblocks = 0;
+    size_t lds_bytes = 0;
+    // timing
+    bool timing = false;
+    struct Mark { hipEvent_t a, b; int kind; };
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> pool;
+    double ms[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+};
+
+static std::string g_create_error;
+
+static sf_status fail(sf_ctx c, sf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf; else g_create_error = buf;
+    return s;
+}
+
+static sf_status hip_fail(sf_ctx c, hipError_t e, const char* what) {
+    if (c) c->hip_failed = true;
+    return fail(c, SF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                                        \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);                  \
+    } while (0)
+
+static int level_halo(int N, int Ns) { return std::max(N, 2) + 2 * Ns; }
+
+static int level_steps(float max_flow, int h) {   // h is 0-based
+    double v = ceil((double)max_flow / ldexp(1.0, h));
+    return std::max(1, (int)v);
+}
+
+static bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
+static sf_status check_alive(sf_ctx c) {
+    if (!c) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL context");
+    if (c->hip_failed) return fail(c, SF_ERR_HIP, "context unusable after a HIP failure: %s",
+                                   c->err.c_str());
+    return SF_OK;
+}
+
+static const float kDefaultAlpha[5] = {300.0f, 1000.0f, 1.0f, 1.0f, 1.0f};
+
+static sf_status validate_config(const sf_config* cfg, sf_config* out) {
+    if (!cfg) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL config");
+    sf_config c = *cfg;
+    if (c.rows < 2 || c.cols < 2) return fail(nullptr, SF_ERR_INVALID_ARG, "rows and cols must be >= 2");
+    if (c.rows > (1 << 15) || c.cols > (1 << 15))
+        return fail(nullptr, SF_ERR_INVALID_ARG, "rows and cols must be <= 32768");
+    if (c.levels < 1 || c.levels > kMaxLevels)
+        return fail(nullptr, SF_ERR_INVALID_ARG, "levels must be in [1, %d]", kMaxLevels);
+    int r = c.rows, q = c.cols;
+    for (int h = 1; h < c.levels; ++h) { r = (r + 1) / 2; q = (q + 1) / 2; }
+    if (r < 2 || q < 2)
+        return fail(nullptr, SF_ERR_INVALID_ARG, "the coarsest level must be at least 2x2");
+    if (!(c.max_flow_px >= 0.0f) || !isfinite(c.max_flow_px) || c.max_flow_px > 4096.0f)
+        return fail(nullptr, SF_ERR_INVALID_ARG, "max_flow_px must be finite and in [0, 4096]");
+    for (int h = 0; h < c.levels; ++h)
+        if (c.smooth_iters[h] < 0 || c.smooth_iters[h] > 16)
+            return fail(nullptr, SF_ERR_INVALID_ARG, "smooth_iters must be in [0, 16]");
+    bool allzero = true;
+    for (int k = 0; k < 5; ++k) allzero = allzero && c.alpha[k] == 0.0f;
+    if (allzero) memcpy(c.alpha, kDefaultAlpha, sizeof kDefaultAlpha);
+    for (int k = 0; k < 5; ++k)
+        if (!(c.alpha[k] >= 0.0f) || !isfinite(c.alpha[k]))
+            return fail(nullptr, SF_ERR_INVALID_ARG, "alpha must be finite and >= 0");
+    if (!(c.alpha[2] > 0.0f)) return fail(nullptr, SF_ERR_INVALID_ARG, "alpha_3 must be > 0");
+    if (!(c.alpha[3] + c.alpha[4] > 0.0f))
+        return fail(nullptr, SF_ERR_INVALID_ARG, "alpha_4 + alpha_5 must be > 0");
+    if (c.storage != SF_FP32 && c.storage != SF_FP16)
+        return fail(nullptr, SF_ERR_INVALID_ARG, "storage must be SF_FP32 or SF_FP16");
+    if (c.update != SF_UPDATE_PLAIN && c.update != SF_UPDATE_LEARNED)
+        return fail(nullptr, SF_ERR_INVALID_ARG, "unknown update kind");
+    if (c.update == SF_UPDATE_LEARNED)
+        return fail(nullptr, SF_ERR_UNSUPPORTED, "the learned update is not available in this build");
+    if (c.read_flags & ~(uint32_t)(SF_READ_DOMINANT_LITERAL | SF_READ_SOURCE_LITERAL |
+                                    SF_READ_NO_CFL_CLAMP))
+        return fail(nullptr, SF_ERR_INVALID_ARG, "unknown read_flags bits");
+    for (int h = 0; h < c.levels; ++h) {
+        int halo = level_halo(level_steps(c.max_flow_px, h), c.smooth_iters[h]);
+        if (2 * halo >= kRegion)
+            return fail(nullptr, SF_ERR_UNSUPPORTED,
+                        "level %d needs a halo of %d pixels (max(N,2) + 2*smooth); at most %d fit",
+                        h + 1, halo, (kRegion - 1) / 2);
+    }
+    for (int h = c.levels; h < kMaxLevels; ++h) c.smooth_iters[h] = 0;
+    *out = c;
+    return SF_OK;
+}
+
+// Tiles of level h: balanced split of the level into tiles of at most 64 - 2*halo.
+static void choose_tiles(sf_ctx c, int h) {
+    LevelDev& L = c->lv[h];
+    const int tmax = kRegion - 2 * L.halo;
+    int tw = c->user_tw[h], th = c->user_th[h];
+    if (tw <= 0 || th <= 0) {
+        int nx = (L.cols + tmax - 1) / tmax, ny = (L.rows + tmax - 1) / tmax;
+        tw = (L.cols + nx - 1) / nx;
+        th = (L.rows + ny - 1) / ny;
+    }
+    L.tw = tw;
+    L.th = th;
+    L.tiles_x = (L.cols + tw - 1) / tw;
+    L.tiles_y = (L.rows + th - 1) / th;
+}
+
+static void layout_blocks(sf_ctx c) {
+    int b = 0;
+    size_t lds = 0;
+    for (int h = 0; h < c->H; ++h) {
+        LevelDev& L = c->lv[h];
+        choose_tiles(c, h);
+        L.block0 = b;
+        b += L.tiles_x * L.tiles_y;
+        const int RH = L.th + 2 * L.halo, RW = L.tw + 2 * L.halo;
+        lds = std::max(lds, (size_t)kPlanes * RH * (size_t)(RW | 1) * sizeof(float));
+    }
+    c->nblocks = b;
+    c->lds_bytes = lds;
+}
+
+extern "C" {
+
+sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out) {
+    if (!out) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL output pointer");
+    *out = nullptr;
+    sf_config c;
+    sf_status st = validate_config(cfg, &c);
+    if (st != SF_OK) return st;
+    sf_ctx ctx = new (std::nothrow) sf_ctx_s();
+    if (!ctx) return fail(nullptr, SF_ERR_OOM, "host allocation failed");
+    ctx->cfg = c;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->H = c.levels;
+    ctx->esize = c.storage == SF_FP16 ? 2 : 4;
+    // sizes and pitches
+    size_t total = 0;
+    const size_t align = 256;
+    auto plane_bytes = [&](int rows, int pitch) {
+        return ((size_t)rows * pitch * ctx->esize + align - 1) / align * align;
+    };
+    int r = c.rows, q = c.cols;
+    for (int h = 0; h < ctx->H; ++h) {
+        LevelDev& L = ctx->lv[h];
+        L.rows = r;
+        L.cols = q;
+        const int per_row = (int)(align / ctx->esize);
+        L.pitch = (q + per_row - 1) / per_row * per_row;
+        L.top = h == ctx->H - 1;
+        const int nplanes = 2 * (3 + (L.top ? 0 : 3) + 2) + (h > 0 ? 2 : 0);
+        total += nplanes * plane_bytes(r, L.pitch);
+        r = (r + 1) / 2;
+        q = (q + 1) / 2;
+    }
+    total += align + sizeof(LevelDev) * kMaxLevels;
+    hipError_t e = hipMalloc((void**)&ctx->arena, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return fail(nullptr, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                    "hipMalloc of %zu bytes failed: %s", total, hipGetErrorString(e));
+    }
+    ctx->arena_bytes = total;
+    char* p = ctx->arena;
+    auto take = [&](size_t n) { char* x = p; p += n; return (void*)x; };
+    for (int h = 0; h < ctx->H; ++h) {
+        LevelDev& L = ctx->lv[h];
+        const size_t pb = plane_bytes(L.rows, L.pitch);
+        for (int par = 0; par < 2; ++par) {
+            for (int k = 0; k < 3; ++k) L.w[par][k] = take(pb);
+            for (int k = 0; k < 3; ++k) L.dw[par][k] = L.top ? nullptr : take(pb);
+            L.rho[par] = take(pb);
+            L.Y[par] = take(pb);
+        }
+        L.Ym = h > 0 ? take(pb) : nullptr;
+        L.Rm = h > 0 ? take(pb) : nullptr;
+    }
+    ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * kMaxLevels);
+    e = hipMemsetAsync(ctx->arena, 0, total, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->arena);
+        delete ctx;
+        return fail(nullptr, SF_ERR_HIP, "clearing the arena failed: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return SF_OK;
+}
+
+static sf_status upload_levels(sf_ctx c) {
+    layout_blocks(c);
+    HIP_TRY(c, prepare_kernels(std::max<size_t>(c->lds_bytes, 65536)));
+    HIP_TRY(c, hipMemcpyAsync(c->lv_dev, c->lv, sizeof(LevelDev) * kMaxLevels,
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SF_OK;
+}
+
+sf_status sf_set_camera(sf_ctx c, const sf_camera* cam) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!cam) return fail(c, SF_ERR_INVALID_ARG, "NULL camera");
+    if (!(cam->fx > 0) || !(cam->fy > 0) || !isfinite(cam->fx) || !isfinite(cam->fy) ||
+        !isfinite(cam->cx) || !isfinite(cam->cy))
+        return fail(c, SF_ERR_INVALID_ARG, "fx, fy must be finite and > 0, cx, cy finite");
+    c->cam[0] = cam->fx; c->cam[1] = cam->fy; c->cam[2] = cam->cx; c->cam[3] = cam->cy;
+    const sf_config& cf = c->cfg;
+    for (int h = 0; h < c->H; ++h) {
+        LevelDev& L = c->lv[h];
+        const double s = ldexp(1.0, h);
+        const double fx = cam->fx / s, fy = cam->fy / s, cx = cam->cx / s, cy = cam->cy / s;
+        L.ifx = (float)(1.0 / fx);
+        L.ify = (float)(1.0 / fy);
+        L.cxn = (float)(cx / fx);
+        L.cyn = (float)(cy / fy);
+        L.fx = (float)fx;
+        L.N = level_steps(cf.max_flow_px, h);
+        L.Ns = cf.smooth_iters[h];
+        L.halo = level_halo(L.N, L.Ns);
+        const double dmu0 = 1.0 / sqrt(fx * fx + 1.0);
+        L.g1 = (float)(cf.alpha[0] / (dmu0 * dmu0));
+        L.g2 = (float)(cf.alpha[1] / (dmu0 * dmu0));
+        L.g3 = cf.alpha[2];
+        L.g4 = cf.alpha[3];
+        L.g5 = cf.alpha[4];
+        L.qscale = (float)(1.0 / dmu0);   // half storage keeps flow in pixels per frame
+    }
+    sf_status s2 = upload_levels(c);
+    if (s2 != SF_OK) return s2;
+    c->camera = true;
+    c->frames = 0;
+    c->parity = 0;
+    c->dt_prev = 0.0;
+    return SF_OK;
+}
+
+sf_status sf_set_tile(sf_ctx c, int32_t level, int32_t tw, int32_t th) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (level < 1 || level > c->H) return fail(c, SF_ERR_INVALID_ARG, "level out of range");
+    const int h = level - 1;
+    if (!(tw == 0 && th == 0)) {
+        const int halo = level_halo(level_steps(c->cfg.max_flow_px, h), c->cfg.smooth_iters[h]);
+        if (tw < 1 || th < 1 || tw + 2 * halo > kRegion || th + 2 * halo > kRegion)
+            return fail(c, SF_ERR_INVALID_ARG, "tile %dx%d with halo %d exceeds %d", tw, th, halo,
+                        kRegion);
+    }
+    c->user_tw[h] = tw;
+    c->user_th[h] = th;
+    if (c->camera) return upload_levels(c);
+    return SF_OK;
+}
+
+// -- timing ---------------------------------------------------------------------------------
+static hipEvent_t pool_get(sf_ctx c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct TimedLaunch {
+    sf_ctx c;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(sf_ctx c_, int k) : c(c_), kind(k) {
+        if (c->timing) {
+            a = pool_get(c);
+            b = pool_get(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    void done() {
+        if (c->timing && a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->marks.push_back({a, b, kind});
+        }
+    }
+};
+
+sf_status sf_set_timing(sf_ctx c, int32_t enable) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    c->timing = enable != 0;
+    return SF_OK;
+}
+
+sf_status sf_kernel_times(sf_ctx c, double* ms3, int64_t* launches3, int32_t reset) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!ms3 || !launches3) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& m : c->marks) {
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, m.a, m.b));
+        c->ms[m.kind] += ms;
+        c->launches[m.kind] += 1;
+        c->pool.push_back(m.a);
+        c->pool.push_back(m.b);
+    }
+    c->marks.clear();
+    for (int k = 0; k < 3; ++k) {
+        ms3[k] = c->ms[k];
+        launches3[k] = c->launches[k];
+    }
+    if (reset)
+        for (int k = 0; k < 3; ++k) { c->ms[k] = 0.0; c->launches[k] = 0; }
+    return SF_OK;
+}
+
+// -- frames ---------------------------------------------------------------------------------
+static sf_status run_pyramid(sf_ctx c, const void* Y, const void* rho) {
+    for (int h = 0; h + 1 < c->H; ++h) {
+        const void* ys = h == 0 ? Y : c->lv[h].Ym;
+        const void* rs = h == 0 ? rho : c->lv[h].Rm;
+        const int sp = h == 0 ? c->lv[0].cols : c->lv[h].pitch;
+        TimedLaunch t(c, 0);
+        HIP_TRY(c, launch_pyramid(c->cfg.storage, c->lv, c->lv_dev, h, ys, rs, sp, c->stream));
+        t.done();
+    }
+    return SF_OK;
+}
+
+sf_status sf_push_frame(sf_ctx c, const void* Y, const void* rho, double dt) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!c->camera) return fail(c, SF_ERR_STATE, "sf_set_camera must be called before pushing");
+    if (!is_device_ptr(Y) || !is_device_ptr(rho))
+        return fail(c, SF_ERR_INVALID_ARG, "Y and rho must be device pointers");
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, SF_ERR_INVALID_ARG, "dt must be > 0 and finite");
+    st = run_pyramid(c, Y, rho);
+    if (st != SF_OK) return st;
+    if (c->frames == 0) {
+        for (int h = 0; h < c->H; ++h) {
+            const void* ym = h == 0 ? Y : c->lv[h].Ym;
+            const void* rm = h == 0 ? rho : c->lv[h].Rm;
+            const int mp = h == 0 ? c->lv[0].cols : c->lv[h].pitch;
+            HIP_TRY(c, launch_init(c->cfg.storage, c->lv, c->lv_dev, h, ym, rm, mp, c->stream));
+        }
+        c->parity = 0;
+        c->frames = 1;
+        c->dt_prev = dt;
+        return SF_OK;
+    }
+    StepArgs a;
+    a.lv = c->lv_dev;
+    a.nlev = c->H;
+    a.Y1 = Y;
+    a.R1 = rho;
+    a.parity = c->parity;
+    a.scale = dt == c->dt_prev ? 1.0f : (float)(dt / c->dt_prev);
+    a.flags = c->cfg.read_flags;
+    {
+        TimedLaunch t(c, 1);
+        HIP_TRY(c, launch_step(c->cfg.storage, a, c->nblocks, c->lds_bytes, c->stream));
+        t.done();
+    }
+    const int q = 1 - c->parity;
+    for (int h = c->H - 2; h >= 0; --h) {
+        TimedLaunch t(c, 2);
+        HIP_TRY(c, launch_reconstruct(c->cfg.storage, c->lv, c->lv_dev, h, q, c->stream));
+        t.done();
+    }
+    c->parity = q;
+    c->frames += 1;
+    c->dt_prev = dt;
+    return SF_OK;
+}
+
+sf_status sf_get_flow(sf_ctx c, int32_t kind, void* out) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (kind < SF_FLOW_W_RAD_S || kind > SF_FLOW_W_FRAME)
+        return fail(c, SF_ERR_INVALID_ARG, "unknown flow kind %d", kind);
+    if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
+    if (!c->camera || c->frames == 0) return fail(c, SF_ERR_STATE, "no frame has been pushed");
+    HIP_TRY(c, launch_output(c->cfg.storage, c->lv, c->lv_dev, c->parity, kind,
+                             (float)(1.0 / c->dt_prev), (float*)out, c->stream));
+    return SF_OK;
+}
+
+// -- state blob -----------------------------------------------------------------------------
+struct BlobHeader {
+    uint32_t magic;
+    uint32_t version;
+    int32_t levels;
+    int32_t initialised;
+    double dt_prev;
+    int64_t frames;
+};
+static_assert(sizeof(BlobHeader) == 32, "blob header is 32 bytes");
+static const uint32_t kMagic = 0x54535346u;   // 'SFST'
+
+static size_t blob_bytes(sf_ctx c) {
+    size_t n = sizeof(BlobHeader);
+    for (int h = 0; h < c->H; ++h) {
+        const LevelDev& L = c->lv[h];
+        n += (size_t)(L.top ? 5 : 8) * L.rows * L.cols * sizeof(float);
+    }
+    return n;
+}
+
+sf_status sf_state_size(sf_ctx c, size_t* bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!bytes) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
+    *bytes = blob_bytes(c);
+    return SF_OK;
+}
+
+static float half_to_float(uint16_t h) {
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    uint32_t exp = (h >> 10) & 0x1fu;
+    uint32_t man = h & 0x3ffu;
+    uint32_t bits;
+    if (exp == 0) {
+        if (man == 0) {
+            bits = sign;
+        } else {   // subnormal: renormalise
+            int e = -1;
+            do { ++e; man <<= 1; } while (!(man & 0x400u));
+            bits = sign | ((uint32_t)(127 - 15 - e) << 23) | ((man & 0x3ffu) << 13);
+        }
+    } else if (exp == 31) {
+        bits = sign | 0x7f800000u | (man << 13);
+    } else {
+        bits = sign | ((exp + 127 - 15) << 23) | (man << 13);
+    }
+    float f;
+    memcpy(&f, &bits, 4);
+    return f;
+}
+
+static uint16_t float_to_half(float f) {   // round to nearest even
+    uint32_t x;
+    memcpy(&x, &f, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u;
+    const uint32_t ax = x & 0x7fffffffu;
+    if (ax >= 0x7f800000u) return (uint16_t)(sign | 0x7c00u | (ax > 0x7f800000u ? 0x200u : 0));
+    if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);          // overflow -> inf
+    if (ax < 0x38800000u) {                                              // subnormal or zero
+        if (ax < 0x33000000u) return (uint16_t)sign;
+        const uint32_t e = ax >> 23;
+        const uint32_t m = (ax & 0x7fffffu) | 0x800000u;
+        const uint32_t shift = 126 - e;                                  // 14..24
+        const uint32_t rem = m & ((1u << shift) - 1);
+        const uint32_t half = 1u << (shift - 1);
+        uint32_t q = m >> shift;
+        if (rem > half || (rem == half && (q & 1))) ++q;
+        return (uint16_t)(sign | q);
+    }
+    uint32_t q = ((ax - 0x38000000u) >> 13);
+    const uint32_t rem = ax & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (q & 1))) ++q;
+    return (uint16_t)(sign | q);
+}
+
+static sf_status copy_plane(sf_ctx c, bool to_host, void* dev, int pitch, int rows, int cols,
+                            float* host, float mul, std::vector<uint16_t>& scratch) {
+    if (c->esize == 4) {
+        if (to_host) {
+            HIP_TRY(c, hipMemcpy2DAsync(host, cols * 4, dev, (size_t)pitch * 4, cols * 4, rows,
+                                        hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (mul != 1.0f)
+                for (size_t k = 0; k < (size_t)rows * cols; ++k) host[k] *= mul;
+        } else {
+            std::vector<float> tmp(host, host + (size_t)rows * cols);
+            if (mul != 1.0f)
+                for (auto& v : tmp) v *= mul;
+            HIP_TRY(c, hipMemcpy2DAsync(dev, (size_t)pitch * 4, tmp.data(), cols * 4, cols * 4,
+                                        rows, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+        }
+        return SF_OK;
+    }
+    scratch.resize((size_t)rows * cols);
+    if (to_host) {
+        HIP_TRY(c, hipMemcpy2DAsync(scratch.data(), cols * 2, dev, (size_t)pitch * 2, cols * 2,
+                                    rows, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < scratch.size(); ++k) host[k] = half_to_float(scratch[k]) * mul;
+    } else {
+        for (size_t k = 0; k < scratch.size(); ++k) scratch[k] = float_to_half(host[k] * mul);
+        HIP_TRY(c, hipMemcpy2DAsync(dev, (size_t)pitch * 2, scratch.data(), cols * 2, cols * 2,
+                                    rows, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return SF_OK;
+}
+
+static sf_status transfer_state(sf_ctx c, bool to_host, float* f) {
+    std::vector<uint16_t> scratch;
+    for (int h = 0; h < c->H; ++h) {
+        LevelDev& L = c->lv[h];
+        const size_t n = (size_t)L.rows * L.cols;
+        const float fin = c->esize == 2 ? 1.0f / L.qscale : 1.0f;    // stored -> rad/frame
+        const float mul = to_host ? fin : 1.0f / fin;
+        const int par = c->parity;
+        for (int k = 0; k < 3; ++k, f += n) {
+            sf_status s = copy_plane(c, to_host, L.w[par][k], L.pitch, L.rows, L.cols, f, mul, scratch);
+            if (s != SF_OK) return s;
+        }
+        if (!L.top)
+            for (int k = 0; k < 3; ++k, f += n) {
+                sf_status s = copy_plane(c, to_host, L.dw[par][k], L.pitch, L.rows, L.cols, f, mul,
+                                         scratch);
+                if (s != SF_OK) return s;
+            }
+        sf_status s = copy_plane(c, to_host, L.rho[par], L.pitch, L.rows, L.cols, f, 1.0f, scratch);
+        if (s != SF_OK) return s;
+        f += n;
+        s = copy_plane(c, to_host, L.Y[par], L.pitch, L.rows, L.cols, f, 1.0f, scratch);
+        if (s != SF_OK) return s;
+        f += n;
+    }
+    return SF_OK;
+}
+
+sf_status sf_get_state(sf_ctx c, void* host_blob, size_t bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!host_blob) return fail(c, SF_ERR_INVALID_ARG, "NULL blob");
+    if (bytes != blob_bytes(c)) return fail(c, SF_ERR_INVALID_ARG, "blob must be %zu bytes", blob_bytes(c));
+    if (!c->camera) return fail(c, SF_ERR_STATE, "no camera set");
+    BlobHeader hd{kMagic, 1u, c->H, c->frames > 0 ? 1 : 0, c->dt_prev, c->frames};
+    memcpy(host_blob, &hd, sizeof hd);
+    if (c->frames == 0) {
+        memset((char*)host_blob + sizeof hd, 0, bytes - sizeof hd);
+        return SF_OK;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return transfer_state(c, true, (float*)((char*)host_blob + sizeof hd));
+}
+
+sf_status sf_set_state(sf_ctx c, const void* host_blob, size_t bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!host_blob) return fail(c, SF_ERR_INVALID_ARG, "NULL blob");
+    if (bytes != blob_bytes(c)) return fail(c, SF_ERR_INVALID_ARG, "blob must be %zu bytes", blob_bytes(c));
+    if (!c->camera) return fail(c, SF_ERR_STATE, "no camera set");
+    BlobHeader hd;
+    memcpy(&hd, host_blob, sizeof hd);
+    if (hd.magic != kMagic || hd.version != 1u || hd.levels != c->H)
+        return fail(c, SF_ERR_INVALID_ARG, "blob header does not match this context");
+    if (hd.initialised && !(hd.dt_prev > 0.0 && isfinite(hd.dt_prev)))
+        return fail(c, SF_ERR_INVALID_ARG, "blob dt_prev must be > 0");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!hd.initialised) {
+        c->frames = 0;
+        c->parity = 0;
+        return SF_OK;
+    }
+    std::vector<float> tmp((bytes - sizeof hd) / sizeof(float));
+    memcpy(tmp.data(), (const char*)host_blob + sizeof hd, bytes - sizeof hd);
+    c->parity = 0;
+    sf_status s = transfer_state(c, false, tmp.data());
+    if (s != SF_OK) return s;
+    c->frames = std::max<int64_t>(1, hd.frames);
+    c->dt_prev = hd.dt_prev;
+    return SF_OK;
+}
+
+sf_status sf_destroy(sf_ctx c) {
+    if (!c) return SF_OK;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& m : c->marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->arena) (void)hipFree(c->arena);
+    delete c;
+    return SF_OK;
+}
+
+const char* sf_last_error(sf_ctx c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

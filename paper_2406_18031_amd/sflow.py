@@ -1,0 +1,270 @@
+"""Python binding of libsflow (include/sflow.h): argument marshalling only.
+
+The functions below carry the C names and forward to the library through ctypes; every
+step of the filter runs in the library's HIP kernels.  Torch is used for device memory and
+streams: image and output arguments are torch CUDA tensors, and the context stream is the
+torch stream current at sf_create (unless one is given).  If the library has not been
+built, importing this module raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsflow.so")
+
+SF_OK = 0
+SF_ERR_INVALID_ARG = -1
+SF_ERR_STATE = -2
+SF_ERR_OOM = -3
+SF_ERR_HIP = -4
+SF_ERR_UNSUPPORTED = -5
+SF_ERR_NUMERIC = -6
+
+SF_FP32, SF_FP16 = 0, 1
+SF_UPDATE_PLAIN, SF_UPDATE_LEARNED = 0, 1
+SF_READ_DOMINANT_LITERAL, SF_READ_SOURCE_LITERAL, SF_READ_NO_CFL_CLAMP = 1, 2, 4
+SF_FLOW_W_RAD_S, SF_FLOW_TANGENT_PX, SF_FLOW_NORMAL_PX, SF_FLOW_RHO, SF_FLOW_W_FRAME = 0, 1, 2, 3, 4
+SF_MAX_LEVELS = 8
+FLOW_COMPONENTS = {SF_FLOW_W_RAD_S: 3, SF_FLOW_TANGENT_PX: 2, SF_FLOW_NORMAL_PX: 1,
+                   SF_FLOW_RHO: 1, SF_FLOW_W_FRAME: 3}
+DEFAULT_ALPHA = (300.0, 1000.0, 1.0, 1.0, 1.0)
+
+
+class sf_config(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("max_flow_px", ctypes.c_float),
+                ("smooth_iters", ctypes.c_int32 * SF_MAX_LEVELS),
+                ("alpha", ctypes.c_float * 5), ("storage", ctypes.c_int32),
+                ("update", ctypes.c_int32), ("read_flags", ctypes.c_uint32)]
+
+
+class sf_camera(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double)]
+
+
+class SflowError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"sflow status {status}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2406_18031_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, st = ctypes.c_void_p, ctypes.c_int
+    sig = {
+        "sf_create": (st, [ctypes.POINTER(sf_config), vp, ctypes.POINTER(vp)]),
+        "sf_set_camera": (st, [vp, ctypes.POINTER(sf_camera)]),
+        "sf_push_frame": (st, [vp, vp, vp, ctypes.c_double]),
+        "sf_get_flow": (st, [vp, ctypes.c_int32, vp]),
+        "sf_state_size": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "sf_get_state": (st, [vp, vp, ctypes.c_size_t]),
+        "sf_set_state": (st, [vp, vp, ctypes.c_size_t]),
+        "sf_destroy": (st, [vp]),
+        "sf_last_error": (ctypes.c_char_p, [vp]),
+        "sf_set_tile": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+        "sf_set_timing": (st, [vp, ctypes.c_int32]),
+        "sf_kernel_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_state_size",
+            "sf_get_state", "sf_set_state", "sf_destroy", "sf_last_error", "sf_set_tile",
+            "sf_set_timing", "sf_kernel_times")
+
+
+def _check(status: int, ctx) -> None:
+    if status != SF_OK:
+        msg = lib.sf_last_error(ctx)
+        raise SflowError(status, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def make_config(rows: int, cols: int, levels: int, max_flow_px: float,
+                smooth_iters: Sequence[int], alpha=DEFAULT_ALPHA, storage: int = SF_FP32,
+                update: int = SF_UPDATE_PLAIN, read_flags: int = 0) -> sf_config:
+    c = sf_config()
+    c.rows, c.cols, c.levels = rows, cols, levels
+    c.max_flow_px = max_flow_px
+    for k, s in enumerate(list(smooth_iters)[:SF_MAX_LEVELS]):
+        c.smooth_iters[k] = int(s)
+    for k, a in enumerate(alpha):
+        c.alpha[k] = float(a)
+    c.storage, c.update, c.read_flags = storage, update, read_flags
+    return c
+
+
+# ---- the C calls, same names ------------------------------------------------------------
+def sf_create(cfg: sf_config, stream=None) -> int:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    out = ctypes.c_void_p()
+    _check(lib.sf_create(ctypes.byref(cfg), ctypes.c_void_p(stream), ctypes.byref(out)), None)
+    return out.value
+
+
+def sf_set_camera(ctx: int, fx: float, fy: float, cx: float, cy: float) -> None:
+    cam = sf_camera(fx, fy, cx, cy)
+    _check(lib.sf_set_camera(ctx, ctypes.byref(cam)), ctx)
+
+
+def sf_push_frame(ctx: int, Y, rho, dt: float) -> None:
+    _check(lib.sf_push_frame(ctx, _ptr(Y), _ptr(rho), float(dt)), ctx)
+
+
+def sf_get_flow(ctx: int, kind: int, out) -> None:
+    _check(lib.sf_get_flow(ctx, kind, _ptr(out)), ctx)
+
+
+def sf_state_size(ctx: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.sf_state_size(ctx, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def sf_get_state(ctx: int) -> bytes:
+    n = sf_state_size(ctx)
+    buf = ctypes.create_string_buffer(n)
+    _check(lib.sf_get_state(ctx, buf, n), ctx)
+    return buf.raw
+
+
+def sf_set_state(ctx: int, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib.sf_set_state(ctx, buf, len(blob)), ctx)
+
+
+def sf_destroy(ctx: int) -> None:
+    _check(lib.sf_destroy(ctx), None)
+
+
+def sf_last_error(ctx: Optional[int]) -> str:
+    m = lib.sf_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def sf_set_tile(ctx: int, level: int, tw: int, th: int) -> None:
+    _check(lib.sf_set_tile(ctx, level, tw, th), ctx)
+
+
+def sf_set_timing(ctx: int, enable: bool) -> None:
+    _check(lib.sf_set_timing(ctx, 1 if enable else 0), ctx)
+
+
+def sf_kernel_times(ctx: int, reset: bool = False):
+    ms = (ctypes.c_double * 3)()
+    n = (ctypes.c_int64 * 3)()
+    _check(lib.sf_kernel_times(ctx, ms, n, 1 if reset else 0), ctx)
+    return list(ms), list(n)
+
+
+# ---- state blob layout (header + float32 planes, see include/sflow.h) ---------------------
+def level_shapes(rows: int, cols: int, levels: int):
+    out, r, c = [], rows, cols
+    for _ in range(levels):
+        out.append((r, c))
+        r, c = (r + 1) // 2, (c + 1) // 2
+    return out
+
+
+def unpack_state(blob: bytes, rows: int, cols: int, levels: int):
+    """-> (list of per-level dicts {w (R,C,3), dw (R,C,3), rho, Y}, dt_prev, frames)."""
+    hdr = np.frombuffer(blob[:32], dtype=np.uint8)
+    magic, version, nlev, init = np.frombuffer(hdr[:16].tobytes(), dtype=np.int32)
+    dt_prev = float(np.frombuffer(hdr[16:24].tobytes(), dtype=np.float64)[0])
+    frames = int(np.frombuffer(hdr[24:32].tobytes(), dtype=np.int64)[0])
+    data = np.frombuffer(blob[32:], dtype=np.float32)
+    out, off = [], 0
+    for h, (R, C) in enumerate(level_shapes(rows, cols, levels)):
+        n = R * C
+        st = {}
+        st["w"] = data[off:off + 3 * n].reshape(3, R, C).transpose(1, 2, 0).astype(np.float64)
+        off += 3 * n
+        if h < levels - 1:
+            st["dw"] = data[off:off + 3 * n].reshape(3, R, C).transpose(1, 2, 0).astype(np.float64)
+            off += 3 * n
+        st["rho"] = data[off:off + n].reshape(R, C).astype(np.float64)
+        off += n
+        st["Y"] = data[off:off + n].reshape(R, C).astype(np.float64)
+        off += n
+        out.append(st)
+    return out, dt_prev, frames
+
+
+def pack_state(state, rows: int, cols: int, levels: int, dt_prev: float, frames: int = 1) -> bytes:
+    head = np.zeros(32, dtype=np.uint8)
+    head[:16] = np.frombuffer(np.array([0x54535346, 1, levels, 1], dtype=np.uint32).tobytes(),
+                              dtype=np.uint8)
+    head[16:24] = np.frombuffer(np.array([dt_prev], dtype=np.float64).tobytes(), dtype=np.uint8)
+    head[24:32] = np.frombuffer(np.array([frames], dtype=np.int64).tobytes(), dtype=np.uint8)
+    parts = [head.tobytes()]
+    for h, st in enumerate(state):
+        parts.append(np.ascontiguousarray(np.asarray(st["w"]).transpose(2, 0, 1), np.float32).tobytes())
+        if h < levels - 1:
+            parts.append(np.ascontiguousarray(np.asarray(st["dw"]).transpose(2, 0, 1), np.float32).tobytes())
+        parts.append(np.ascontiguousarray(st["rho"], np.float32).tobytes())
+        parts.append(np.ascontiguousarray(st["Y"], np.float32).tobytes())
+    return b"".join(parts)
+
+
+class Filter:
+    """Convenience wrapper owning one context; inputs are torch CUDA tensors."""
+
+    def __init__(self, rows, cols, levels, max_flow_px, smooth_iters, fx, fy, cx, cy,
+                 alpha=DEFAULT_ALPHA, storage=SF_FP32, read_flags=0, stream=None):
+        self.rows, self.cols, self.levels = rows, cols, levels
+        self.storage = storage
+        self.cfg = make_config(rows, cols, levels, max_flow_px, smooth_iters, alpha, storage,
+                               SF_UPDATE_PLAIN, read_flags)
+        self.ctx = sf_create(self.cfg, stream)
+        sf_set_camera(self.ctx, fx, fy, cx, cy)
+
+    def push(self, Y, rho, dt):
+        sf_push_frame(self.ctx, Y, rho, dt)
+
+    def flow(self, kind=SF_FLOW_W_FRAME, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((FLOW_COMPONENTS[kind], self.rows, self.cols), dtype=torch.float32,
+                              device="cuda")
+        sf_get_flow(self.ctx, kind, out)
+        return out
+
+    def get_state(self):
+        return unpack_state(sf_get_state(self.ctx), self.rows, self.cols, self.levels)
+
+    def set_state(self, state, dt_prev, frames=1):
+        sf_set_state(self.ctx, pack_state(state, self.rows, self.cols, self.levels, dt_prev, frames))
+
+    def close(self):
+        if self.ctx:
+            sf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

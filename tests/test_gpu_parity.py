@@ -1,0 +1,143 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Bar (per frame, finest level): mean endpoint error |w_gpu - w_oracle| / dmu at most
+1e-3 px in FP32 storage and 2e-2 px in FP16 storage; state planes (rho, Yhat) within the
+float32 rounding of their values.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import epe_px, gpu_flow_frame, log, make_pair, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FP32_EPE = 1e-3
+FP16_EPE = 2e-2
+
+
+def _random_frames(rng, R, C, n, nan_frac=0.05):
+    out = []
+    base = rng.random((R + 8, C + 8))
+    for k in range(n):
+        # a textured pattern drifting by about a pixel per frame, plus noise
+        Y = 0.6 * np.roll(base, (k, 2 * k), axis=(0, 1))[:R, :C] + 0.2 * rng.random((R, C))
+        rho = 0.2 + 0.3 * rng.random((R, C))
+        rho[rng.random((R, C)) < nan_frac] = np.nan
+        out.append((Y, rho))
+    return out
+
+
+def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None, bar=FP32_EPE,
+         compare_state=True):
+    o, g = make_pair(R, C, H, mf, smooth, cam, storage=storage, read_flags=read_flags)
+    dmu = o.grids[0].dmu
+    worst = 0.0
+    for k, (Y, rho) in enumerate(frames):
+        dt = 1.0 if dts is None else dts[k]
+        Yr, rr = rounded(Y, storage), rounded(rho, storage)
+        dtype = "float16" if storage == 1 else "float32"
+        log(f"  frame {k} {R}x{C} H={H} storage={storage} flags={read_flags}")
+        g.push(to_dev(Y, dtype), to_dev(rho, dtype), dt)
+        o.push(Yr, rr, dt)
+        e = epe_px(gpu_flow_frame(g), o.flow("w_frame"), dmu)
+        worst = max(worst, e["mean"])
+        assert e["mean"] <= bar, (k, e)
+        if compare_state and storage == 0:
+            st, dt_prev, _ = g.get_state()
+            assert dt_prev == dt
+            for h in range(H):
+                np.testing.assert_allclose(st[h]["Y"], o.state[h]["Y"], atol=2e-6)
+                np.testing.assert_allclose(st[h]["rho"], o.state[h]["rho"], atol=2e-5, rtol=1e-4)
+    g.close()
+    return worst
+
+
+@pytest.mark.parametrize("H", [1, 3])
+def test_brute_8x8(H):
+    rng = np.random.default_rng(80 + H)
+    frames = _random_frames(rng, 8, 8, 5)
+    w = _run(frames, 8, 8, H, 2.0 * H, [2] * H, (8.8, 8.8, 3.8, 3.3))
+    log("8x8 H", H, "worst mean EPE", w)
+
+
+@pytest.mark.parametrize("flags", [0, 1 | 2, 4])
+def test_ragged_multi_tile(flags):
+    """Sizes that span several tiles per level with ragged last tiles, missing depth, a change
+    of dt mid-sequence, and the alternative readings."""
+    rng = np.random.default_rng(7 + flags)
+    R, C = 150, 131
+    frames = _random_frames(rng, R, C, 5)
+    dts = [0.01, 0.01, 0.01, 0.02, 0.02]
+    w = _run(frames, R, C, 3, 6.0, [2, 3, 1], (120.0, 110.0, 64.2, 73.9), read_flags=flags,
+             dts=dts)
+    log("ragged flags", flags, "worst mean EPE", w)
+
+
+def test_plane64_sequence():
+    """The 64x64 one-level sinusoid-plane workload, all 20 frames."""
+    from synth.workloads import workload
+    wl = workload("plane64")
+    seq = wl["build"]()
+    from synth.scenes import render_sequence
+    Y, rho, _ = render_sequence(seq)
+    c = seq.camera
+    w = _run(list(zip(Y, rho)), 64, 64, 1, wl["max_flow_px"], wl["smooth"],
+             (c.fx, c.fy, c.cx, c.cy), dts=[seq.dt] * len(Y))
+    log("plane64 worst mean EPE", w)
+
+
+def test_static_scene_zero_flow():
+    from paper_2406_18031_amd import sflow
+    rng = np.random.default_rng(3)
+    Y = to_dev(rng.random((70, 90)))
+    rho = to_dev(0.3 + rng.random((70, 90)))
+    f = sflow.Filter(70, 90, 2, 3.0, [2, 4], 80.0, 80.0, 44.5, 34.5)
+    for _ in range(6):
+        f.push(Y, rho, 1.0 / 300)
+    w = f.flow(sflow.SF_FLOW_W_RAD_S)
+    assert float(w.abs().max()) == 0.0
+    f.close()
+
+
+def test_tiling_does_not_change_results():
+    """Any tile shape computes the same per-pixel arithmetic: results are bitwise equal."""
+    from paper_2406_18031_amd import sflow
+    rng = np.random.default_rng(11)
+    frames = [(to_dev(Y), to_dev(r)) for Y, r in _random_frames(rng, 97, 113, 4)]
+    outs = []
+    for tiles in (None, [(16, 12), (9, 30), (5, 5)]):
+        f = sflow.Filter(97, 113, 3, 5.0, [2, 2, 3], 100.0, 100.0, 56.0, 48.0)
+        if tiles:
+            for h, (tw, th) in enumerate(tiles):
+                sflow.sf_set_tile(f.ctx, h + 1, tw, th)
+        for Y, r in frames:
+            f.push(Y, r, 0.01)
+        outs.append(f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy())
+        f.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_repeat_runs_bitwise_identical():
+    from paper_2406_18031_amd import sflow
+    rng = np.random.default_rng(12)
+    frames = [(to_dev(Y), to_dev(r)) for Y, r in _random_frames(rng, 64, 80, 4)]
+    outs = []
+    for _ in range(2):
+        f = sflow.Filter(64, 80, 2, 4.0, [2, 4], 70.0, 70.0, 40.0, 31.0)
+        for Y, r in frames:
+            f.push(Y, r, 0.01)
+        outs.append(f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy())
+        f.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_fp16_storage_plane64():
+    from synth.workloads import workload
+    from synth.scenes import render_sequence
+    wl = workload("plane64")
+    seq = wl["build"]()
+    Y, rho, _ = render_sequence(seq)
+    c = seq.camera
+    w = _run(list(zip(Y, rho)), 64, 64, 1, wl["max_flow_px"], wl["smooth"],
+             (c.fx, c.fy, c.cx, c.cy), storage=1, dts=[seq.dt] * len(Y), bar=FP16_EPE)
+    log("plane64 fp16 worst mean EPE", w)
