@@ -14,8 +14,9 @@ LIB = os.path.join(PKG, "libsflow.so")
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sflow_kernels.hip", "sflow_abi.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# -packed-fp32-ops: no packed FP32 instructions in device code
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+# -packed-fp32-ops: no packed FP32 instructions in device code; -ffp-contract=off: only the
+# FMAs written out (fmaf) are fused, so every code path rounds alike
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]

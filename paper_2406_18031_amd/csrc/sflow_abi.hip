@@ -170,11 +170,9 @@ static void layout_blocks(sf_ctx c) {
         choose_tiles(c, h);
         L.block0 = b;
         b += L.tiles_x * L.tiles_y;
-        const int RH = L.th + 2 * L.halo, RW = L.tw + 2 * L.halo;
-        lds = std::max(lds, (size_t)kPlanes * RH * (size_t)(RW | 1) * sizeof(float));
     }
     c->nblocks = b;
-    c->lds_bytes = lds;
+    c->lds_bytes = std::max(lds, kLdsBytes);
 }
 
 extern "C" {

@@ -12,7 +12,9 @@ namespace sflow {
 constexpr int kMaxLevels = SF_MAX_LEVELS;
 constexpr int kBlock = 512;          // threads per block of the fused level kernel
 constexpr int kRegion = 64;          // max rows/columns of a tile plus its halo
-constexpr int kPlanes = 8;           // float planes of the region held in LDS
+// LDS of the fused level kernel: the larger of the row-pass exchange buffers
+// (2 buffers x 8 waves x 2 rows x 8 fields x 64 lanes) and the update planes (5 x 64 x 64)
+constexpr size_t kLdsBytes = 5 * kRegion * 64 * sizeof(float);
 
 // Per-level parameters, uploaded once per camera to device memory.
 struct LevelDev {

@@ -44,12 +44,6 @@ __device__ __forceinline__ float gtap(int a) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Pinhole geometry of pixel (i, j).  With r = ((j - cx)/fx, (i - cy)/fy, 1) = (x, y, 1),
 // eta = r/|r| and the next column's ray r_n = r +- e_x/fx (the previous column in the last
 // column), P_eta eta_n is parallel to P_eta e_x, which gives in closed form
@@ -102,9 +96,105 @@ __device__ __forceinline__ float minabs_diff(float c, float nxt, float prv) {
 // ------------------------------------------------------------------------------------------
 // fused level step
 // ------------------------------------------------------------------------------------------
+// Lane l of wave w holds column gj0 + l of region rows [8w, 8w + 8) in registers.
+// Cross-lane moves must run with every lane of the wave active: the empty asm pins each DPP
+// move where it is written, so that the compiler cannot sink it into a branch of a later
+// select (a DPP read from a lane disabled by EXEC returns the reading lane's own value).
+__device__ __forceinline__ float dpp_prev(float v) {   // value of the lane to the left
+    float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xF, 0xF,
+        false));
+    asm volatile("" : "+v"(r));
+    return r;
+}
+__device__ __forceinline__ float dpp_next(float v) {   // value of the lane to the right
+    float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xF, 0xF,
+        false));
+    asm volatile("" : "+v"(r));
+    return r;
+}
+
+// Column neighbours with clamping at the image's left/right border (the border pixel is its
+// own neighbour).  BORDER is false for tiles that touch neither border.  Call unconditionally.
+template <bool BORDER>
+__device__ __forceinline__ float nb_prev(float v, bool at_left) {
+    const float p = dpp_prev(v);
+    return BORDER && at_left ? v : p;
+}
+template <bool BORDER>
+__device__ __forceinline__ float nb_next(float v, bool at_right) {
+    const float p = dpp_next(v);
+    return BORDER && at_right ? v : p;
+}
+__device__ __forceinline__ float clamp_prev(float v, bool keep) {
+    const float p = dpp_prev(v);
+    return keep ? v : p;
+}
+__device__ __forceinline__ float clamp_next(float v, bool keep) {
+    const float p = dpp_next(v);
+    return keep ? v : p;
+}
+
+// Geometry of pixel (i, j) for the register-strip kernel: y, 1/|r|, fx |r_n|, x/(1 + y^2)
+// and B = fx |r_n| |r| / (1 + y^2) (see pixel_geo for the closed forms).
+__device__ __forceinline__ void row_geo(const LevelDev& L, int i, float x, float xn, float& y,
+                                        float& rinv, float& fxrn, float& xi, float& B) {
+    y = fmaf((float)i, L.ify, -L.cyn);
+    const float yy1 = fmaf(y, y, 1.0f);
+    const float r2 = fmaf(x, x, yy1);
+    rinv = rsqrtf(r2);
+    fxrn = L.fx * sqrtf(fmaf(xn, xn, yy1));
+    const float inv = 1.0f / yy1;
+    xi = x * inv;
+    B = fxrn * (r2 * rinv) * inv;
+}
+
+constexpr int kNW = kBlock / 64;        // waves per block
+constexpr int kRPW = kRegion / kNW;     // region rows per wave
+
+// One column (beta_1) half-step of every valid row held by this wave.
+template <int NF, bool BORDER>
+__device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&grinv)[kRPW],
+                                            const float (&gfxrn)[kRPW], const float (&gxi)[kRPW],
+                                            const float (&gy)[kRPW], float x, int wi0, int ci0,
+                                            int ci1, bool at_left, bool at_right, float dt,
+                                            float fN, float dtsig, bool dom_lit, bool cfl) {
+#pragma unroll
+    for (int r = 0; r < kRPW; ++r) {
+        const int i = wi0 + r;
+        if (i < ci0 || i >= ci1) continue;            // wave-uniform
+        const float wx = F[r][0], wy = F[r][1], wz = F[r][2];
+        const float t = fmaf(gy[r], wy, wz);
+        const float u = gfxrn[r] * fmaf(-gxi[r], t, wx);      // b1.w / dmu
+        const float um = nb_prev<BORDER>(u, at_left);
+        const float up = nb_next<BORDER>(u, at_right);
+        const bool larger_next = fabsf(up) > fabsf(um);
+        float uh = dom_lit ? (larger_next ? um : up) : (larger_next ? up : um);
+        if (cfl) uh = fminf(fmaxf(uh, -fN), fN);
+        const float s = grinv[r] * fmaf(x, wx, t);           // <eta, w>
+        const float k1 = dt * uh;
+        const float c = fmaf(-dtsig, s, 1.0f);
+        const bool back = uh > 0.0f;
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const float f = F[r][k];
+            const float fm = nb_prev<BORDER>(f, at_left);
+            const float fp = nb_next<BORDER>(f, at_right);
+            const float D = back ? f - fm : fp - f;
+            const float cf = (NF == 8 && k == 7) ? f : c * f;   // the image has no source term
+            F[r][k] = fmaf(-k1, D, cf);
+        }
+    }
+}
+
 template <typename T, bool TOP>
 __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L, int h, int t,
                                            float* lds) {
+    constexpr int NF = TOP ? 4 : 8;   // top: w(3), rho; lower: w(3), dw(3), rho, Yhat
+    constexpr int NW = kNW;
+    constexpr int RPW = kRPW;
+    constexpr int KR = TOP ? 3 : 6;   // index of rho among the fields
     const int R = L.rows, C = L.cols;
     const int ty = t / L.tiles_x;
     const int tx = t - ty * L.tiles_x;
@@ -113,174 +203,205 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const int halo = L.halo;
     const int gi0 = ti0 - halo, gj0 = tj0 - halo;
     const int RH = L.th + 2 * halo, RW = L.tw + 2 * halo;
-    const int P = RW | 1;           // odd pitch: column passes read LDS without bank conflicts
-    const int PS = RH * P;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    constexpr int NW = kBlock / 64;
-    constexpr bool top = TOP;
     const int par = a.parity;
-    constexpr int nf = TOP ? 4 : 8; // transported fields: w(3), rho | w(3), dw(3), rho, Y
-    // plane of field k: top {w0, w1, w2, rho} -> {0, 1, 2, 3}; lower -> {0..7}
-    auto plane = [&](int k) -> float* { return lds + k * PS; };
-    constexpr int prho = TOP ? 3 : 6;
-
+    const int wi0 = gi0 + wave * RPW;             // image row of this wave's register row 0
+    const int j = gj0 + lane;                     // image column of this lane
+    const bool lane_ok = lane < RW && j >= 0 && j < C;
+    const bool at_left = j == 0, at_right = j == C - 1;
+    const bool border = gj0 <= 0 || gj0 + RW >= C;   // the region holds an image column border
+    const bool left_b = border && at_left, right_b = border && at_right;
+    // rows of the region held by this wave that lie in the image
     const int vi0 = max(gi0, 0), vi1 = min(gi0 + RH, R);
     const int vj0 = max(gj0, 0), vj1 = min(gj0 + RW, C);
 
-    // ---- load frame-k state of the region -----------------------------------------------
+    // ---- geometry of this lane's pixels (pinhole closed forms, see pixel_geo) -------------
+    const float x = fmaf((float)j, L.ifx, -L.cxn);
+    const float xn = x + (j < C - 1 ? L.ifx : -L.ifx);
+    float grinv[RPW], gfxrn[RPW], gxi[RPW], gB[RPW], gy[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+        row_geo(L, wi0 + r, x, xn, gy[r], grinv[r], gfxrn[r], gxi[r], gB[r]);
+    // rows just above and below this wave's strip, for the row-pass halo (same arithmetic as
+    // the owning wave, so results do not depend on where strips start)
+    float yA, BA, yBl, BBl;
+    {
+        float t0, t1, t2;
+        row_geo(L, wi0 - 1, x, xn, yA, t0, t1, t2, BA);
+        row_geo(L, wi0 + RPW, x, xn, yBl, t0, t1, t2, BBl);
+    }
+
+    // ---- load the frame-k state of the region into registers ------------------------------
+    float F[RPW][NF];
     {
         const float fs = flow_in_scale<T>(L) * a.scale;
-        for (int i = vi0 + wave; i < vi1; i += NW) {
-            const int j = gj0 + lane;
-            if (lane < RW && j >= vj0 && j < vj1) {
-                const size_t gidx = (size_t)i * L.pitch + j;
-                const int li = (i - gi0) * P + lane;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) plane(k)[li] = ldv((const T*)L.w[par][k], gidx) * fs;
-                plane(prho)[li] = ldv((const T*)L.rho[par], gidx);
-                if (!top) {
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            const bool ok = lane_ok && i >= vi0 && i < vi1;
+            const size_t g = (size_t)(ok ? i : 0) * L.pitch + (ok ? j : 0);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        plane(3 + k)[li] = ldv((const T*)L.dw[par][k], gidx) * fs;
-                    plane(7)[li] = ldv((const T*)L.Y[par], gidx);
+            for (int k = 0; k < NF; ++k) F[r][k] = 0.0f;
+            if (ok) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) F[r][k] = ldv((const T*)L.w[par][k], g) * fs;
+                F[r][KR] = ldv((const T*)L.rho[par], g);
+                if (!TOP) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) F[r][3 + k] = ldv((const T*)L.dw[par][k], g) * fs;
+                    F[r][7] = ldv((const T*)L.Y[par], g);
                 }
             }
         }
     }
-    __syncthreads();
 
-    // ---- prediction: N steps of column then row half-steps --------------------------------
+    // ---- prediction -------------------------------------------------------------------------
     const int N = L.N;
     const float dt = 1.0f / (float)N;
     const float fN = (float)N;
     const float sig = (a.flags & SF_READ_SOURCE_LITERAL) ? 1.0f : 0.5f;
+    const float dtsig = dt * sig;
     const bool dom_lit = (a.flags & SF_READ_DOMINANT_LITERAL) != 0;
     const bool cfl = (a.flags & SF_READ_NO_CFL_CLAMP) == 0;
     int ci0 = vi0, ci1 = vi1, cj0 = vj0, cj1 = vj1;
+    float* XB = lds;   // [2][NW][2][NF][64] boundary rows of every wave, double-buffered
 
     for (int n = 0; n < N; ++n) {
-#pragma unroll
-        for (int axis = 0; axis < 2; ++axis) {   // 0: column pass (along j), 1: row pass (along i)
-            const bool colp = axis == 0;
-            // the new valid interval along the pass axis shrinks on interior sides
-            const int lo = colp ? cj0 : ci0, hi = colp ? cj1 : ci1;
-            const int ext = colp ? C : R;
-            const int nlo = lo > 0 ? lo + 1 : lo;
-            const int nhi = hi < ext ? hi - 1 : hi;
-            // lines orthogonal to the pass, one per wave; lane = position along the pass
-            const int l0 = colp ? ci0 : cj0, l1 = colp ? ci1 : cj1;
-            const int g0 = colp ? gj0 : gi0;
-            const int span = colp ? RW : RH;
-            const int stride = colp ? 1 : P;
-            for (int line = l0 + wave; line < l1; line += NW) {
-                const int pos = g0 + lane;            // image coordinate along the pass
-                const bool act = lane < span && pos >= lo && pos < hi;
-                const int i = colp ? line : pos;
-                const int j = colp ? pos : line;
-                const int base = colp ? (line - gi0) * P + lane : lane * P + (line - gj0);
-                float f[8];
-                float u = 0.0f;
-                Geo g = {};
-                if (act) {
-#pragma unroll
-                    for (int k = 0; k < nf; ++k) f[k] = plane(k)[base];
-                    g = pixel_geo(L, i, j);
-                    u = colp ? flow_u(g, f[0], f[1], f[2]) : flow_v(g, f[0], f[1], f[2]);
-                }
-                float um = __shfl_up(u, 1);
-                float up = __shfl_down(u, 1);
-                if (pos == 0) um = u;
-                if (pos == ext - 1) up = u;
-                const bool upd = act && pos >= nlo && pos < nhi;
-                float nv[8];
-                if (upd) {
-                    const bool larger_next = fabsf(up) > fabsf(um);
-                    float uh = dom_lit ? (larger_next ? um : up) : (larger_next ? up : um);
-                    if (cfl) uh = fminf(fmaxf(uh, -fN), fN);
-                    const float s = normal_s(g, f[0], f[1], f[2]);
-                    const bool back = uh > 0.0f;
-                    const int nb = back ? (pos > 0 ? base - stride : base)
-                                        : (pos < ext - 1 ? base + stride : base);
-#pragma unroll
-                    for (int k = 0; k < nf; ++k) {
-                        const float fn = plane(k)[nb];
-                        const float D = back ? f[k] - fn : fn - f[k];
-                        const float sg = (!TOP && k == 7) ? 0.0f : sig;
-                        nv[k] = f[k] - dt * (uh * D + sg * f[k] * s);
-                    }
-                }
-                wave_sync();
-                if (upd) {
-#pragma unroll
-                    for (int k = 0; k < nf; ++k) plane(k)[base] = nv[k];
-                }
-                wave_sync();
-            }
-            __syncthreads();
-            if (colp) { cj0 = nlo; cj1 = nhi; } else { ci0 = nlo; ci1 = nhi; }
-        }
-    }
+        // column half-step: neighbours from adjacent lanes
+        if (border)
+            column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, wi0, ci0, ci1, at_left, at_right,
+                                  dt, fN, dtsig, dom_lit, cfl);
+        else
+            column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, wi0, ci0, ci1, at_left, at_right,
+                                   dt, fN, dtsig, dom_lit, cfl);
+        cj0 = cj0 > 0 ? cj0 + 1 : cj0;
+        cj1 = cj1 < C ? cj1 - 1 : cj1;
 
-    // ---- update ---------------------------------------------------------------------------
+        // row half-step: neighbours from the rows above/below, across waves through LDS
+        float* xb = XB + (n & 1) * (NW * 2 * NF * 64);
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            xb[((wave * 2 + 0) * NF + k) * 64 + lane] = F[0][k];
+            xb[((wave * 2 + 1) * NF + k) * 64 + lane] = F[RPW - 1][k];
+        }
+        __syncthreads();
+        float above[NF], below[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            above[k] = wave > 0 ? xb[(((wave - 1) * 2 + 1) * NF + k) * 64 + lane] : 0.0f;
+            below[k] = wave < NW - 1 ? xb[(((wave + 1) * 2 + 0) * NF + k) * 64 + lane] : 0.0f;
+        }
+        const int ni0 = ci0 > 0 ? ci0 + 1 : ci0;
+        const int ni1 = ci1 < R ? ci1 - 1 : ci1;
+        float v[RPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) v[r] = gB[r] * fmaf(-gy[r], F[r][2], F[r][1]);
+        const float vA = BA * fmaf(-yA, above[2], above[1]);
+        const float vB = BBl * fmaf(-yBl, below[2], below[1]);
+        float prev[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) prev[k] = above[k];
+        float vprev = vA;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            float cur[NF];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) cur[k] = F[r][k];
+            const float vc = v[r];
+            if (i >= ni0 && i < ni1) {                // wave-uniform
+                const bool top_b = i == 0, bot_b = i == R - 1;
+                const float vm = top_b ? vc : vprev;
+                const float vp = bot_b ? vc : (r + 1 < RPW ? v[r + 1 < RPW ? r + 1 : r] : vB);
+                const bool larger_next = fabsf(vp) > fabsf(vm);
+                float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
+                if (cfl) vh = fminf(fmaxf(vh, -fN), fN);
+                const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
+                const float k1 = dt * vh;
+                const float c = fmaf(-dtsig, s, 1.0f);
+                const bool back = vh > 0.0f;
+#pragma unroll
+                for (int k = 0; k < NF; ++k) {
+                    const float fm = top_b ? cur[k] : prev[k];
+                    const float fp = bot_b ? cur[k] : (r + 1 < RPW ? F[r + 1 < RPW ? r + 1 : r][k] : below[k]);
+                    const float D = back ? cur[k] - fm : fp - cur[k];
+                    const float cf = (!TOP && k == 7) ? cur[k] : c * cur[k];
+                    F[r][k] = fmaf(-k1, D, cf);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NF; ++k) prev[k] = cur[k];
+            vprev = vc;
+        }
+        ci0 = ni0;
+        ci1 = ni1;
+    }
+    __syncthreads();   // the LDS below is reused for the update phase
+
+    // ---- update -------------------------------------------------------------------------------
     const int Ns = L.Ns;
     const int si0 = max(ti0 - 2 * Ns, 0), si1 = min(ti1 + 2 * Ns, R);
     const int sj0 = max(tj0 - 2 * Ns, 0), sj1 = min(tj1 + 2 * Ns, C);
     const int mi0 = max(si0 - 2, 0), mi1 = min(si1 + 2, R);
     const int mj0 = max(sj0 - 2, 0), mj1 = min(sj1 + 2, C);
-    float* YN = plane(top ? 4 : 0);
-    float* HG = plane(top ? 5 : 1);
-    float* HD = plane(top ? 6 : 2);
-    float* X[3] = {plane(top ? 0 : 3), plane(top ? 1 : 4), plane(top ? 2 : 5)};
+    float* PHG = lds;                    // [64 rows][64 lanes]
+    float* PHD = lds + kRegion * 64;
+    float* PT = lds + 2 * kRegion * 64;  // [3][64][64] smoothing
     const T* Ymeas = (const T*)(h == 0 ? a.Y1 : L.Ym);
     const T* Rmeas = (const T*)(h == 0 ? a.R1 : L.Rm);
     const int mp = h == 0 ? C : L.pitch;
+    const bool mcol = lane < RW && j >= mj0 && j < mj1;
 
-    for (int i = mi0 + wave; i < mi1; i += NW) {
-        const int j = gj0 + lane;
-        if (lane < RW && j >= mj0 && j < mj1)
-            YN[(i - gi0) * P + lane] = ldv(Ymeas, (size_t)i * mp + j);
-    }
-    __syncthreads();
-    // horizontal taps of the image model: HG = g * Y, HD = (g d) * Y along j
-    for (int i = mi0 + wave; i < mi1; i += NW) {
-        const int j = gj0 + lane;
-        if (lane < RW && j >= sj0 && j < sj1) {
-            const int row = (i - gi0) * P - gj0;
-            float hg = 0.0f, hd = 0.0f;
+    // horizontal taps of the image model in registers
 #pragma unroll
-            for (int bb = -2; bb <= 2; ++bb) {
-                const float y = YN[row + clampi(j + bb, 0, C - 1)];
-                hg = fmaf(gtap(bb), y, hg);
-                hd = fmaf(gtap(bb) * (float)bb, y, hd);
-            }
-            HG[(i - gi0) * P + lane] = hg;
-            HD[(i - gi0) * P + lane] = hd;
-        }
+    for (int r = 0; r < RPW; ++r) {
+        const int i = wi0 + r;
+        if (i < mi0 || i >= mi1) continue;           // wave-uniform
+        const float y = mcol ? ldv(Ymeas, (size_t)i * mp + j) : 0.0f;
+        const float ym1 = clamp_prev(y, left_b);
+        const float ym2 = clamp_prev(ym1, left_b);
+        const float yp1 = clamp_next(y, right_b);
+        const float yp2 = clamp_next(yp1, right_b);
+        float hg = 0.0f, hd = 0.0f;
+        hg = fmaf(0.0625f, ym2, hg);
+        hg = fmaf(0.25f, ym1, hg);
+        hg = fmaf(0.375f, y, hg);
+        hg = fmaf(0.25f, yp1, hg);
+        hg = fmaf(0.0625f, yp2, hg);
+        hd = fmaf(-0.125f, ym2, hd);
+        hd = fmaf(-0.25f, ym1, hd);
+        hd = fmaf(0.25f, yp1, hd);
+        hd = fmaf(0.125f, yp2, hd);
+        const int row = wave * RPW + r;
+        PHG[row * 64 + lane] = hg;
+        PHD[row * 64 + lane] = hd;
     }
     __syncthreads();
 
+    // vertical taps, depth model and the least-squares solve, per pixel
     {
         const float sg3 = L.g3;
         T* Yout = (T*)L.Y[1 - par];
         T* Rout = (T*)L.rho[1 - par];
         const T* Yold = (const T*)L.Y[par];
         const T* Rold = (const T*)L.rho[par];
-        for (int i = si0 + wave; i < si1; i += NW) {
-            const int j = gj0 + lane;
-            if (!(lane < RW && j >= sj0 && j < sj1)) continue;
-            const int li = (i - gi0) * P + lane;
-            // brightness model: vertical taps
+        const bool scol = lane < RW && j >= sj0 && j < sj1;
+        const bool tcol = j >= tj0 && j < tj1 && lane < RW;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            if (i < si0 || i >= si1) continue;       // wave-uniform
+            if (!scol) continue;
             float Yh = 0.0f, d1 = 0.0f, d2 = 0.0f;
 #pragma unroll
             for (int aa = -2; aa <= 2; ++aa) {
-                const int r = (clampi(i + aa, 0, R - 1) - gi0) * P + lane;
-                const float hg = HG[r], hd = HD[r];
+                const int rr = (clampi(i + aa, 0, R - 1) - gi0) * 64 + lane;
+                const float hg = PHG[rr], hd = PHD[rr];
                 Yh = fmaf(gtap(aa), hg, Yh);
                 d1 = fmaf(gtap(aa), hd, d1);
                 d2 = fmaf(gtap(aa) * (float)aa, hg, d2);
             }
-            // depth model from the level's measured inverse depth
             const size_t gm = (size_t)i * mp;
             const float rc = ldv(Rmeas, gm + j);
             const bool rv = !isnan(rc);
@@ -291,89 +412,89 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 r2 = minabs_diff(rc, ldv(Rmeas, (size_t)min(i + 1, R - 1) * mp + j),
                                  ldv(Rmeas, (size_t)max(i - 1, 0) * mp + j));
             }
-            // geometry
-            const Geo g = pixel_geo(L, i, j);
-            const float ex = g.x * g.rinv, ey = g.y * g.rinv, ez = g.rinv;
-            const float q = sqrtf(fmaf(g.y, g.y, 1.0f)) * g.rinv;    // sqrt(1 - eta_x^2)
+            // tangent basis and spacing at (i, j)
+            const float rinv = grinv[r];
+            const float ex = x * rinv, ey = gy[r] * rinv, ez = rinv;
+            const float q = sqrtf(fmaf(gy[r], gy[r], 1.0f)) * rinv;   // sqrt(1 - eta_x^2)
             const float iq = 1.0f / q;
             const float b1x = q, b1y = -ex * ey * iq, b1z = -ex * ez * iq;
-            const float b2y = ez * iq, b2z = -ey * iq;              // b2x = 0
-            const float dmu = q / g.fxrn;
-            // data terms in pixel units: E = dmu^2 (a_hat . xi + c_hat) with xi = x / dmu
+            const float b2y = ez * iq, b2z = -ey * iq;
+            const float dmu = q / gfxrn[r];
             const float aYx = b1x * d1, aYy = fmaf(b1y, d1, b2y * d2), aYz = fmaf(b1z, d1, b2z * d2);
             float aRx = 0.0f, aRy = 0.0f, aRz = 0.0f, cR = 0.0f;
-            const float rprior = top ? ldv(Rold, (size_t)i * L.pitch + j) : plane(prho)[li];
-            const float Yprior = top ? ldv(Yold, (size_t)i * L.pitch + j) : plane(7)[li];
+            const size_t gs = (size_t)i * L.pitch + j;
+            const float rprior = TOP ? ldv(Rold, gs) : F[r][KR];
+            const float Yprior = TOP ? ldv(Yold, gs) : F[r][7 % NF];
             if (rv) {
-                const float k = dmu * rc;
-                aRx = fmaf(k, ex, b1x * r1);
-                aRy = fmaf(k, ey, fmaf(b1y, r1, b2y * r2));
-                aRz = fmaf(k, ez, fmaf(b1z, r1, b2z * r2));
+                const float kk = dmu * rc;
+                aRx = fmaf(kk, ex, b1x * r1);
+                aRy = fmaf(kk, ey, fmaf(b1y, r1, b2y * r2));
+                aRz = fmaf(kk, ez, fmaf(b1z, r1, b2z * r2));
                 cR = rc - rprior;
             }
             const float cY = Yh - Yprior;
             const float idmu = 1.0f / dmu;
-            const float x0 = X[0][li] * idmu, y0 = X[1][li] * idmu, z0 = X[2][li] * idmu;
+            constexpr int KX = TOP ? 0 : 3;
+            const float x0 = F[r][KX] * idmu, y0 = F[r][KX + 1] * idmu, z0 = F[r][KX + 2] * idmu;
             const float dmu2 = dmu * dmu;
             const float G1 = L.g1 * dmu2;
             const float G2 = rv ? L.g2 * dmu2 : 0.0f;
             const float res1 = cY + fmaf(aYx, x0, fmaf(aYy, y0, aYz * z0));
             const float res2 = cR + fmaf(aRx, x0, fmaf(aRy, y0, aRz * z0));
-            const float aa = fmaf(aYx, aYx, fmaf(aYy, aYy, aYz * aYz));
+            const float aa2 = fmaf(aYx, aYx, fmaf(aYy, aYy, aYz * aYz));
             const float bb = fmaf(aRx, aRx, fmaf(aRy, aRy, aRz * aRz));
             const float ab = fmaf(aYx, aRx, fmaf(aYy, aRy, aYz * aRz));
             const float cx_ = aYy * aRz - aYz * aRy, cy_ = aYz * aRx - aYx * aRz,
                         cz_ = aYx * aRy - aYy * aRx;
             const float cross2 = fmaf(cx_, cx_, fmaf(cy_, cy_, cz_ * cz_));   // aa bb - ab^2
-            const float det = fmaf(sg3, sg3 + G1 * aa + G2 * bb, G1 * G2 * cross2);
+            const float det = fmaf(sg3, sg3 + G1 * aa2 + G2 * bb, G1 * G2 * cross2);
             const float al = -G1 * fmaf(res1, sg3, G2 * (res1 * bb - ab * res2)) / det;
-            const float be = -G2 * fmaf(res2, sg3, G1 * (res2 * aa - ab * res1)) / det;
-            X[0][li] = fmaf(al, aYx, fmaf(be, aRx, x0)) * dmu;
-            X[1][li] = fmaf(al, aYy, fmaf(be, aRy, y0)) * dmu;
-            X[2][li] = fmaf(al, aYz, fmaf(be, aRz, z0)) * dmu;
-            if (i >= ti0 && i < ti1 && j >= tj0 && j < tj1) {
-                const size_t go = (size_t)i * L.pitch + j;
-                const float rpred = plane(prho)[li];
+            const float be = -G2 * fmaf(res2, sg3, G1 * (res2 * aa2 - ab * res1)) / det;
+            const float rpred = F[r][KR];
+            F[r][KX] = fmaf(al, aYx, fmaf(be, aRx, x0)) * dmu;
+            F[r][KX + 1] = fmaf(al, aYy, fmaf(be, aRy, y0)) * dmu;
+            F[r][KX + 2] = fmaf(al, aYz, fmaf(be, aRz, z0)) * dmu;
+            if (i >= ti0 && i < ti1 && tcol) {
                 const float rn = rv ? (L.g4 * rc + L.g5 * rpred) / (L.g4 + L.g5) : rpred;
-                stv(Rout, go, rn);
-                stv(Yout, go, Yh);
+                stv(Rout, gs, rn);
+                stv(Yout, gs, Yh);
             }
         }
     }
-    __syncthreads();
 
-    // ---- smoothing: N_s passes of the 5x5 average (separable sums, clamped borders) -------
-    float* TMP[3] = {YN, HG, HD};
+    // ---- smoothing: N_s passes of the 5x5 average ---------------------------------------------
+    constexpr int KX = TOP ? 0 : 3;
     for (int sp = 1; sp <= Ns; ++sp) {
-        const int r = 2 * (Ns - sp);
-        const int oi0 = max(ti0 - r, 0), oi1 = min(ti1 + r, R);
-        const int oj0 = max(tj0 - r, 0), oj1 = min(tj1 + r, C);
+        const int rad = 2 * (Ns - sp);
+        const int oi0 = max(ti0 - rad, 0), oi1 = min(ti1 + rad, R);
         const int ii0 = max(oi0 - 2, 0), ii1 = min(oi1 + 2, R);
-        for (int i = ii0 + wave; i < ii1; i += NW) {
-            const int j = gj0 + lane;
-            if (lane < RW && j >= oj0 && j < oj1) {
-                const int row = (i - gi0) * P - gj0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    float s = 0.0f;
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            if (i < ii0 || i >= ii1) continue;        // wave-uniform
+            const int row = wave * RPW + r;
 #pragma unroll
-                    for (int bb = -2; bb <= 2; ++bb) s += X[k][row + clampi(j + bb, 0, C - 1)];
-                    TMP[k][(i - gi0) * P + lane] = s;
-                }
+            for (int k = 0; k < 3; ++k) {
+                const float v0 = F[r][KX + k];
+                const float m1 = clamp_prev(v0, left_b);
+                const float m2 = clamp_prev(m1, left_b);
+                const float p1 = clamp_next(v0, right_b);
+                const float p2 = clamp_next(p1, right_b);
+                PT[(k * kRegion + row) * 64 + lane] = (((m2 + m1) + v0) + p1) + p2;
             }
         }
         __syncthreads();
-        for (int i = oi0 + wave; i < oi1; i += NW) {
-            const int j = gj0 + lane;
-            if (lane < RW && j >= oj0 && j < oj1) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    float s = 0.0f;
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            if (i < oi0 || i >= oi1) continue;        // wave-uniform
 #pragma unroll
-                    for (int aa = -2; aa <= 2; ++aa)
-                        s += TMP[k][(clampi(i + aa, 0, R - 1) - gi0) * P + lane];
-                    X[k][(i - gi0) * P + lane] = s * 0.04f;
-                }
+            for (int k = 0; k < 3; ++k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int aa = -2; aa <= 2; ++aa)
+                    s += PT[(k * kRegion + (clampi(i + aa, 0, R - 1) - gi0)) * 64 + lane];
+                F[r][KX + k] = s * 0.04f;
             }
         }
         __syncthreads();
@@ -382,16 +503,16 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     // ---- store the solved field of the tile -----------------------------------------------
     {
         const float os = flow_out_scale<T>(L);
-        for (int i = ti0 + wave; i < ti1; i += NW) {
-            const int j = tj0 + lane;
-            if (lane < L.tw && j < tj1) {
-                const size_t go = (size_t)i * L.pitch + j;
-                const int li = (i - gi0) * P + (j - gj0);
+        const bool tcol = j >= tj0 && j < tj1 && lane < RW;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    T* dst = (T*)(top ? L.w[1 - par][k] : L.dw[1 - par][k]);
-                    stv(dst, go, X[k][li] * os);
-                }
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            if (i < ti0 || i >= ti1 || !tcol) continue;
+            const size_t go = (size_t)i * L.pitch + j;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T* dst = (T*)(TOP ? L.w[1 - par][k] : L.dw[1 - par][k]);
+                stv(dst, go, F[r][KX + k] * os);
             }
         }
     }
