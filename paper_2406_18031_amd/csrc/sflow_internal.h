@@ -10,11 +10,13 @@
 namespace sflow {
 
 constexpr int kMaxLevels = SF_MAX_LEVELS;
-constexpr int kBlock = 512;          // threads per block of the fused level kernel
+constexpr int kBlock = 1024;         // threads per block of the fused level kernel
 constexpr int kRegion = 64;          // max rows/columns of a tile plus its halo
 // LDS of the fused level kernel: the larger of the row-pass exchange buffers
-// (2 buffers x 8 waves x 2 rows x 8 fields x 64 lanes) and the update planes (5 x 64 x 64)
-constexpr size_t kLdsBytes = 5 * kRegion * 64 * sizeof(float);
+// (2 buffers x waves x 2 rows x 8 fields x 64 lanes) and the update planes (5 x 64 x 64)
+constexpr size_t kLdsXB = 2 * (kBlock / 64) * 2 * 8 * 64 * sizeof(float);
+constexpr size_t kLdsPlanes = 5 * kRegion * 64 * sizeof(float);
+constexpr size_t kLdsBytes = kLdsXB > kLdsPlanes ? kLdsXB : kLdsPlanes;
 
 // Per-level parameters, uploaded once per camera to device memory.
 struct LevelDev {

@@ -96,27 +96,22 @@ __device__ __forceinline__ float minabs_diff(float c, float nxt, float prv) {
 // ------------------------------------------------------------------------------------------
 // fused level step
 // ------------------------------------------------------------------------------------------
-// Lane l of wave w holds column gj0 + l of region rows [8w, 8w + 8) in registers.
-// Cross-lane moves must run with every lane of the wave active: the empty asm pins each DPP
-// move where it is written, so that the compiler cannot sink it into a branch of a later
-// select (a DPP read from a lane disabled by EXEC returns the reading lane's own value).
+// Lane l of wave w holds column gj0 + l of region rows [w R, w R + R) in registers, R = kRPW.
+// Cross-lane moves must run with every lane of the wave active (a DPP read from a lane that
+// EXEC disables does not return that lane's value), so they are only ever called as plain
+// statements, never inside a conditional expression or a lane-dependent branch.  Lanes whose
+// source lies outside the wave read 0; those are region-edge lanes, never valid output.
 __device__ __forceinline__ float dpp_prev(float v) {   // value of the lane to the left
-    float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xF, 0xF,
-        false));
-    asm volatile("" : "+v"(r));
-    return r;
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+        __builtin_bit_cast(int, v), 0x138 /* wave_shr:1 */, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_next(float v) {   // value of the lane to the right
-    float r = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xF, 0xF,
-        false));
-    asm volatile("" : "+v"(r));
-    return r;
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+        __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xF, 0xF, true));
 }
 
 // Column neighbours with clamping at the image's left/right border (the border pixel is its
-// own neighbour).  BORDER is false for tiles that touch neither border.  Call unconditionally.
+// own neighbour).  BORDER is false for tiles that touch neither border.
 template <bool BORDER>
 __device__ __forceinline__ float nb_prev(float v, bool at_left) {
     const float p = dpp_prev(v);
@@ -171,19 +166,21 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
         const float up = nb_next<BORDER>(u, at_right);
         const bool larger_next = fabsf(up) > fabsf(um);
         float uh = dom_lit ? (larger_next ? um : up) : (larger_next ? up : um);
-        if (cfl) uh = fminf(fmaxf(uh, -fN), fN);
+        if (cfl) uh = __builtin_amdgcn_fmed3f(uh, -fN, fN);
         const float s = grinv[r] * fmaf(x, wx, t);           // <eta, w>
-        const float k1 = dt * uh;
+        // upwind step: f - dt (u_hat D + sigma f s) = c f - |dt u_hat| (f - m), where m is the
+        // upwind neighbour (left if u_hat > 0, else right) and c = 1 - dt sigma s
+        const float ak = fabsf(dt * uh);
         const float c = fmaf(-dtsig, s, 1.0f);
         const bool back = uh > 0.0f;
 #pragma unroll
         for (int k = 0; k < NF; ++k) {
             const float f = F[r][k];
-            const float fm = nb_prev<BORDER>(f, at_left);
-            const float fp = nb_next<BORDER>(f, at_right);
-            const float D = back ? f - fm : fp - f;
+            const float db = f - nb_prev<BORDER>(f, at_left);
+            const float df = f - nb_next<BORDER>(f, at_right);
+            const float d = back ? db : df;
             const float cf = (NF == 8 && k == 7) ? f : c * f;   // the image has no source term
-            F[r][k] = fmaf(-k1, D, cf);
+            F[r][k] = fmaf(-ak, d, cf);
         }
     }
 }
@@ -204,7 +201,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const int gi0 = ti0 - halo, gj0 = tj0 - halo;
     const int RH = L.th + 2 * halo, RW = L.tw + 2 * halo;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     const int par = a.parity;
     const int wi0 = gi0 + wave * RPW;             // image row of this wave's register row 0
     const int j = gj0 + lane;                     // image column of this lane
@@ -316,18 +313,18 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 const float vp = bot_b ? vc : (r + 1 < RPW ? v[r + 1 < RPW ? r + 1 : r] : vB);
                 const bool larger_next = fabsf(vp) > fabsf(vm);
                 float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
-                if (cfl) vh = fminf(fmaxf(vh, -fN), fN);
+                if (cfl) vh = __builtin_amdgcn_fmed3f(vh, -fN, fN);
                 const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
-                const float k1 = dt * vh;
+                const float ak = fabsf(dt * vh);
                 const float c = fmaf(-dtsig, s, 1.0f);
                 const bool back = vh > 0.0f;
 #pragma unroll
                 for (int k = 0; k < NF; ++k) {
                     const float fm = top_b ? cur[k] : prev[k];
                     const float fp = bot_b ? cur[k] : (r + 1 < RPW ? F[r + 1 < RPW ? r + 1 : r][k] : below[k]);
-                    const float D = back ? cur[k] - fm : fp - cur[k];
+                    const float d = cur[k] - (back ? fm : fp);
                     const float cf = (!TOP && k == 7) ? cur[k] : c * cur[k];
-                    F[r][k] = fmaf(-k1, D, cf);
+                    F[r][k] = fmaf(-ak, d, cf);
                 }
             }
 #pragma unroll
