@@ -71,7 +71,7 @@ def run_gpu(wl_name, steps, warmup, storage=0):
     from synth.workloads import workload
 
     wl = workload(wl_name)
-    seq = wl["build"]()
+    seq = wl["build"]("cuda")
     cam = seq.camera
     Ys, Rs = render_frames(seq, "cuda")
     if storage == 1:
@@ -103,8 +103,80 @@ def run_gpu(wl_name, steps, warmup, storage=0):
         step(k)
     ms, n = sflow.sf_kernel_times(f.ctx, reset=True)
     sflow.sf_set_timing(f.ctx, False)
+    final = f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
     f.close()
-    return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n)
+    return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n, final=final)
+
+
+def run_batched(n_streams, steps, warmup, storage=0, frames=6):
+    """n_streams independent camera streams of mixed sizes advanced together: one pyramid
+    launch per depth, one level-step launch and one reconstruction launch per depth per
+    frame for all streams.  A step is one frame of every stream plus every stream's output."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    from synth.workloads import stream_mix
+
+    mix = stream_mix(n_streams, n_frames=frames, device="cuda")
+    specs, Ys, Rs = [], [], []
+    for m in mix:
+        seq = m["build"]()
+        c = seq.camera
+        specs.append(dict(rows=seq.rows, cols=seq.cols, levels=m["levels"],
+                          max_flow_px=m["max_flow_px"], smooth=m["smooth"],
+                          camera=(c.fx, c.fy, c.cx, c.cy)))
+        y, r = render_frames(seq, "cuda")
+        if storage == 1:
+            y = [v.half() for v in y]
+            r = [v.half() for v in r]
+        Ys.append(y)
+        Rs.append(r)
+        dt = seq.dt
+    b = sflow.Batch(specs, storage=storage)
+    outs = [torch.empty((3, sp["rows"], sp["cols"]), dtype=torch.float32, device="cuda")
+            for sp in specs]
+    dts = [dt] * len(specs)
+
+    def step(k):
+        b.push([y[k % frames] for y in Ys], [r[k % frames] for r in Rs], dts)
+        for s_ in range(len(specs)):
+            sflow.sf_get_flow_stream(b.ctx, s_, sflow.SF_FLOW_W_RAD_S, outs[s_])
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sflow.sf_set_timing(b.ctx, True)
+    sflow.sf_kernel_times(b.ctx, reset=True)
+    for k in range(warmup, warmup + steps):
+        step(k)
+    ms, n = sflow.sf_kernel_times(b.ctx, reset=True)
+    b.close()
+    px = sum(sp["rows"] * sp["cols"] for sp in specs)
+    step_bytes = step_flops = 0
+    for sp in specs:
+        for L in level_table(sp["rows"], sp["cols"], sp["levels"], sp["max_flow_px"], sp["smooth"]):
+            npx = L["rows"] * L["cols"]
+            step_bytes += npx * step_bytes_per_px(L["top"], 2 if storage == 1 else 4)
+            step_flops += npx * step_flops_per_px(L["top"], L["N"], L["Ns"])
+    step_s = ms[1] / max(1, n[1]) * 1e-3
+    sizes = {}
+    for sp in specs:
+        sizes[sp["rows"]] = sizes.get(sp["rows"], 0) + 1
+    return {
+        "streams": len(specs), "sizes": {f"{k}x{k}": v for k, v in sorted(sizes.items())},
+        "storage": "fp16" if storage == 1 else "fp32",
+        "aggregate_frames_per_s": len(specs) * steps / elapsed,
+        "batch_steps_per_s": steps / elapsed,
+        "mpix_per_s": px * steps / elapsed / 2 ** 20,
+        "kernel_us_per_frame": {k: v / max(1, steps) * 1e3 for k, v in
+                                zip(("pyramid", "level_step", "reconstruct"), ms)},
+        "level_step_tflops": step_flops / step_s / 1e12,
+        "level_step_hbm_gbs": step_bytes / step_s / 1e9,
+    }
 
 
 def cpu_baseline(wl_name, budget_s=20.0):
@@ -138,6 +210,18 @@ def cpu_baseline(wl_name, budget_s=20.0):
                       f"{el:.1f} s, NumPy FP64, one thread)"}
 
 
+def _finest_dmu(seq):
+    """Tangent-plane pixel spacing of the finest grid (closed form for a pinhole)."""
+    import numpy as np
+    c = seq.camera
+    j = np.arange(seq.cols, dtype=np.float64)[None, :]
+    i = np.arange(seq.rows, dtype=np.float64)[:, None]
+    x = (j - c.cx) / c.fx
+    y = (i - c.cy) / c.fy
+    xn = x + np.where(j < seq.cols - 1, 1.0, -1.0) / c.fx
+    return np.sqrt(1 + y * y) / np.sqrt(x * x + y * y + 1) / (c.fx * np.sqrt(xn * xn + y * y + 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +229,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="boxes512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and batched forms")
+    ap.add_argument("--streams", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the filter runs on a single device and this build "
@@ -206,6 +292,29 @@ def main():
         "paper_context": {"hz": 594.7, "workload": "512x512, 2 levels, max flow 8 px, GTX-780",
                           "source": "Table runtime_pyramid_2"},
     }
+    forms = {}
+    if not args.no_forms:
+        import numpy as np
+        r16 = run_gpu(args.workload, args.steps, args.warmup, storage=1)
+        ms16 = r16["kernel_ms"][1] / max(1, r16["kernel_n"][1])
+        dmu = _finest_dmu(seq)
+        d = np.sqrt(np.sum((r16["final"] - r["final"]) ** 2, axis=0)) / dmu
+        forms["fp16_storage"] = {
+            "frames_per_s": args.steps / r16["elapsed"],
+            "level_step_us": ms16 * 1e3,
+            "level_step_hbm_gbs": sum(L["rows"] * L["cols"] * step_bytes_per_px(L["top"], 2)
+                                      for L in levels) / (ms16 * 1e-3) / 1e9,
+            "epe_vs_fp32_storage_px": {"mean": float(d.mean()), "max": float(d.max()),
+                                       "after_frames": args.warmup + 2 * args.steps},
+        }
+        print(f"[bench] fp16 storage: {forms['fp16_storage']['frames_per_s']:.1f} frames/s",
+              flush=True)
+        for st in (0, 1):
+            rb = run_batched(args.streams, max(5, args.steps // 5), 2, storage=st)
+            forms[f"batched_{rb['storage']}"] = rb
+            print(f"[bench] batched {rb['storage']}: {rb['aggregate_frames_per_s']:.1f} "
+                  f"stream-frames/s ({rb['mpix_per_s']:.0f} Mpix/s)", flush=True)
+        res["forms"] = forms
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(res), flush=True)

@@ -102,7 +102,9 @@ typedef struct {
                              alpha_4 + alpha_5 > 0.                                           */
     int32_t storage;      /* SF_FP32 or SF_FP16 (images and state stored in half precision,
                              all arithmetic in float32)                                        */
-    int32_t update;       /* SF_UPDATE_PLAIN (SF_UPDATE_LEARNED needs sf_set_weights)          */
+    int32_t update;       /* SF_UPDATE_PLAIN or SF_UPDATE_LEARNED (then smooth_iters[0] <= 4,
+                             the same for every stream of a batch, and sf_set_learned before
+                             the first push)                                                   */
     uint32_t read_flags;  /* SF_READ_* bits                                                    */
 } sf_config;
 
@@ -152,9 +154,31 @@ sf_status sf_destroy(sf_ctx ctx);
  * pointer stays valid until the next call on the same context. */
 const char* sf_last_error(sf_ctx ctx);
 
-/* Tile shape of the fused level kernel for level h (1-based): output tiles of tw x th
- * pixels; tw + 2*halo_h and th + 2*halo_h must not exceed 64, where halo_h =
- * max(N_h, 2) + 2 * smooth_iters[h-1].  0, 0 restores the built-in choice.  For tuning. */
+/* ---- batches of camera streams -------------------------------------------------------------
+ * A batch context advances up to 64 independent camera streams together: every frame runs one
+ * pyramid launch per pyramid depth, one fused level-step launch over every tile of every level
+ * of every stream, and one reconstruction launch per depth, for all streams at once.  Streams
+ * may differ in size, levels, maximum flow, smoothing, weights and readings, but not in
+ * storage.  sf_create is sf_create_batch with n = 1; the single-stream calls (sf_set_camera,
+ * sf_push_frame, sf_get_flow, sf_state_size, sf_get_state, sf_set_state) return
+ * SF_ERR_INVALID_ARG on a context of more than one stream. */
+sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf_ctx* out);
+sf_status sf_stream_count(sf_ctx ctx, int32_t* n);
+/* cams: host array of n cameras, one per stream; resets every stream */
+sf_status sf_set_cameras(sf_ctx ctx, const sf_camera* cams);
+/* Y, rho: host arrays of n device pointers (one frame per stream); dt: host array of n */
+sf_status sf_push_frames(sf_ctx ctx, const void* const* Y, const void* const* rho,
+                         const double* dt);
+sf_status sf_get_flow_stream(sf_ctx ctx, int32_t stream, int32_t kind, void* out);
+sf_status sf_state_size_stream(sf_ctx ctx, int32_t stream, size_t* bytes);
+sf_status sf_get_state_stream(sf_ctx ctx, int32_t stream, void* host_blob, size_t bytes);
+/* on a batch of more than one stream, only after the first frame has been pushed */
+sf_status sf_set_state_stream(sf_ctx ctx, int32_t stream, const void* host_blob, size_t bytes);
+
+/* Tile shape of the fused level kernel for level h (1-based, all streams that have it):
+ * output tiles of tw x th pixels; tw + 2*halo_h and th + 2*halo_h must not exceed 64, where
+ * halo_h = max(N_h, 2) + 2 * smooth_iters[h-1].  0, 0 restores the built-in choice.  For
+ * tuning. */
 sf_status sf_set_tile(sf_ctx ctx, int32_t level, int32_t tw, int32_t th);
 
 /* Kernel timing for measurement.  When enabled, every push records HIP events around each
@@ -163,6 +187,61 @@ sf_status sf_set_tile(sf_ctx ctx, int32_t level, int32_t tw, int32_t th);
  * last reset (synchronises the stream). */
 sf_status sf_set_timing(sf_ctx ctx, int32_t enable);
 sf_status sf_kernel_times(sf_ctx ctx, double* ms3, int64_t* launches3, int32_t reset);
+
+/* ---- learned update ----------------------------------------------------------------------
+ * An extension beyond the paper, which uses the least-squares update of Section "State
+ * update" at every level.  With update = SF_UPDATE_LEARNED, at the finest level of every
+ * stream a convolutional network (3x3 kernels, 6 -> 16 -> 16 -> 16 -> 3 channels, ReLU after
+ * the first three layers, zero padding; BF16 operands, FP32 accumulation) gives a correction
+ * c (3 values, pixels per frame) of the predicted field x0 (the flow at a top level, the
+ * increment over the parent's flow below it): x_net = x0 + dmu * c.  Its inputs per pixel are
+ * Y_prior - 1/2, Y_new - 1/2, 4 rho (0 where missing) and x0 / dmu / 4 (3), where Y_prior is
+ * the predicted smoothed image and Y_new the new one (Section "State update").
+ * Per pixel, x_net replaces the least-squares solution x_ls unless the least-squares cost of
+ * the step, G1 (aY.d)^2 + G2 (aR.d)^2 + gamma_3 |d|^2 with d = (x_net - x_ls) / dmu (the cost
+ * increase over its minimum at x_ls, in pixel units), exceeds `threshold`; then x_ls is kept
+ * (a "fallback").  Smoothing and the rest of the frame are unchanged.  A threshold < 0 makes
+ * every pixel fall back, which gives exactly the plain update.
+ *
+ * The parameters are FP32, SF_LEARNED_PARAMS values: per layer l = 0..3 the weights
+ * W[3][3][cin][cout] (tap row dy+1, tap column dx+1, input channel, output channel;
+ * out[p] = b + sum W[dy+1][dx+1][c][:] in[p + (dy, dx)][c]) followed by the bias b[cout]. */
+#define SF_LEARNED_PARAMS 5955
+#define SF_UPDATE_INPUT_PLANES 16
+
+/* Load parameters (host, SF_LEARNED_PARAMS finite floats) and the fallback threshold (not
+ * NaN; +inf never falls back); synchronises the stream.  SF_ERR_STATE on a plain context. */
+sf_status sf_set_learned(sf_ctx ctx, const float* params, size_t n, float threshold);
+/* Fallbacks and learned pixels since the last reset (synchronises the stream). */
+sf_status sf_learned_stats(sf_ctx ctx, int64_t* fallbacks, int64_t* pixels, int32_t reset);
+/* Training data of the last frame of one stream (finest level): writes
+ * SF_UPDATE_INPUT_PLANES float32 planes of rows x cols to the device pointer out: the network
+ * inputs (6), x0 (3), x_ls (3), the parent's reconstructed flow (3; 0 at a top level) and dmu
+ * (1).  Flows are in rad/frame, so the correction that reaches a flow w is
+ * (w - parent - x0) / dmu.  SF_ERR_STATE before the second frame. */
+sf_status sf_get_update_inputs(sf_ctx ctx, int32_t stream, float* out);
+
+/* ---- training the learned update's network --------------------------------------------------
+ * A network object runs the network above on a fixed list of up to 64 images (sizes given at
+ * creation, each at most 2^26 pixels, 2^27 in total), on the caller's HIP stream.  Image
+ * tensors are device float32, the images one after the other, each planar [C][rows][cols]
+ * (C = 6 for inputs, 3 for outputs and targets).  Every call synchronises the stream except
+ * sf_net_forward. */
+typedef struct sf_net_s* sf_net;
+sf_status sf_net_create(const int32_t* rows, const int32_t* cols, int32_t n_images,
+                        void* hip_stream, sf_net* out);
+/* set the parameters (host) and reset the optimiser */
+sf_status sf_net_set_params(sf_net net, const float* params, size_t n);
+sf_status sf_net_get_params(sf_net net, float* params, size_t n);
+sf_status sf_net_forward(sf_net net, const float* in, float* out);
+/* One step: forward, the loss mean over all pixels of sqrt(|out - target|^2 + 1e-6), its
+ * gradient by backpropagation, and, when lr > 0, one Adam step (beta 0.9, 0.999, eps 1e-8)
+ * on the parameters.  loss_out (host, 1 float) and grad_out (host, SF_LEARNED_PARAMS floats,
+ * the gradient at the parameters before the step) may be NULL. */
+sf_status sf_net_train_step(sf_net net, const float* in, const float* target, float lr,
+                            float* loss_out, float* grad_out);
+sf_status sf_net_destroy(sf_net net);
+const char* sf_net_last_error(sf_net net);
 
 #ifdef __cplusplus
 }

@@ -1,11 +1,12 @@
 // Host runtime and C ABI of the structure-flow filter (see include/sflow.h).
 //
-// A context owns one device arena holding, per pyramid level, the double-buffered state
-// planes (w, dw, rho, Yhat) and the pyramid's image and inverse-depth planes, all row-major
-// with rows padded to 256 bytes, plus the per-level parameter table the kernels read.  A
-// frame is: pyramid (one launch per level below the finest), one fused level-step launch
-// covering every tile of every level (levels are independent within a frame), then the
-// coarse-to-fine reconstruction (one launch per lower level).
+// A context is a batch of camera streams (one for sf_create).  It owns one device arena that
+// holds, for every (stream, level) "entry", the double-buffered state planes (w, dw, rho,
+// Yhat) and the level's pyramid image and inverse depth, all row-major with rows padded to
+// 256 bytes, plus the entry table the kernels read.  A frame of every stream is: the pyramid
+// (one launch per pyramid depth, all streams together), one fused level-step launch covering
+// every tile of every level of every stream (levels are independent within a frame), then the
+// coarse-to-fine reconstruction (one launch per depth, all streams together).
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -16,30 +17,39 @@
 #include <string>
 #include <vector>
 
+#include "sflow_cnn.h"
 #include "sflow_internal.h"
 
 using namespace sflow;
 
-struct sf_ctx_s {
+struct StreamInfo {
     sf_config cfg{};
-    hipStream_t stream = nullptr;
     int H = 0;
+    int e0 = 0;                    // first entry of the stream (its finest level)
+    double cam[4] = {0, 0, 0, 0};
+    double dt_prev = 0.0;
+};
+
+struct sf_ctx_s {
+    int S = 0;                     // streams
+    int storage = SF_FP32;
+    hipStream_t stream = nullptr;
     int esize = 4;                 // bytes per stored element
     bool camera = false;
     bool hip_failed = false;
-    int64_t frames = 0;            // frames pushed since the camera was set
+    int64_t frames = 0;            // frames pushed since the cameras were set
     int parity = 0;                // state[parity] holds the latest frame
-    double dt_prev = 0.0;
-    double cam[4] = {0, 0, 0, 0};
     std::string err;
     char* arena = nullptr;
     size_t arena_bytes = 0;
-    LevelDev lv[kMaxLevels]{};
+    std::vector<StreamInfo> st;
+    std::vector<LevelDev> lv;      // entries, stream by stream, finest level first
     LevelDev* lv_dev = nullptr;
     int user_tw[kMaxLevels]{};
     int user_th[kMaxLevels]{};
     int nblocks = 0;
     size_t lds_bytes = 0;
+    int max_levels = 0;
     // timing
     bool timing = false;
     struct Mark { hipEvent_t a, b; int kind; };
@@ -47,6 +57,19 @@ struct sf_ctx_s {
     std::vector<hipEvent_t> pool;
     double ms[3] = {0, 0, 0};
     int64_t launches[3] = {0, 0, 0};
+    // learned update (finest level of every stream)
+    bool learned = false;
+    bool weights = false;
+    float threshold = 1.0f;
+    CnnSegs segs{};
+    float* lbuf = nullptr;               // kLearnPlanes x ltotal
+    uint16_t* act[2] = {nullptr, nullptr};   // BF16 NHWC 16-channel activations
+    uint16_t* wf = nullptr;              // packed forward weights [4][9][16][16]
+    uint16_t* wb = nullptr;
+    float* cnn_bias = nullptr;           // [4][16]
+    float* params_dev = nullptr;         // FP32 master weights
+    unsigned long long* fallbacks = nullptr;
+    int64_t learned_pixels = 0;
 };
 
 static std::string g_create_error;
@@ -129,8 +152,9 @@ static sf_status validate_config(const sf_config* cfg, sf_config* out) {
         return fail(nullptr, SF_ERR_INVALID_ARG, "storage must be SF_FP32 or SF_FP16");
     if (c.update != SF_UPDATE_PLAIN && c.update != SF_UPDATE_LEARNED)
         return fail(nullptr, SF_ERR_INVALID_ARG, "unknown update kind");
-    if (c.update == SF_UPDATE_LEARNED)
-        return fail(nullptr, SF_ERR_UNSUPPORTED, "the learned update is not available in this build");
+    if (c.update == SF_UPDATE_LEARNED && c.smooth_iters[0] > 4)
+        return fail(nullptr, SF_ERR_UNSUPPORTED,
+                    "the learned update supports at most 4 smoothing passes at the finest level");
     if (c.read_flags & ~(uint32_t)(SF_READ_DOMINANT_LITERAL | SF_READ_SOURCE_LITERAL |
                                     SF_READ_NO_CFL_CLAMP))
         return fail(nullptr, SF_ERR_INVALID_ARG, "unknown read_flags bits");
@@ -146,12 +170,11 @@ static sf_status validate_config(const sf_config* cfg, sf_config* out) {
     return SF_OK;
 }
 
-// Tiles of level h: balanced split of the level into tiles of at most 64 - 2*halo.
-static void choose_tiles(sf_ctx c, int h) {
-    LevelDev& L = c->lv[h];
+// Tiles of an entry: a balanced split of the level into tiles of at most 64 - 2*halo.
+static void choose_tiles(sf_ctx c, LevelDev& L) {
     const int tmax = kRegion - 2 * L.halo;
-    int tw = c->user_tw[h], th = c->user_th[h];
-    if (tw <= 0 || th <= 0) {
+    int tw = c->user_tw[L.level], th = c->user_th[L.level];
+    if (tw <= 0 || th <= 0 || tw > tmax || th > tmax) {
         int nx = (L.cols + tmax - 1) / tmax, ny = (L.rows + tmax - 1) / tmax;
         tw = (L.cols + nx - 1) / nx;
         th = (L.rows + ny - 1) / ny;
@@ -164,51 +187,93 @@ static void choose_tiles(sf_ctx c, int h) {
 
 static void layout_blocks(sf_ctx c) {
     int b = 0;
-    size_t lds = 0;
-    for (int h = 0; h < c->H; ++h) {
-        LevelDev& L = c->lv[h];
-        choose_tiles(c, h);
+    for (auto& L : c->lv) {
+        choose_tiles(c, L);
         L.block0 = b;
         b += L.tiles_x * L.tiles_y;
     }
     c->nblocks = b;
-    c->lds_bytes = std::max(lds, kLdsBytes);
+    c->lds_bytes = kLdsBytes;
+}
+
+// per-pixel launch over the entries of level `level` (all streams that have it)
+static ElemArgs elem_args(sf_ctx c, int level, int parity) {
+    ElemArgs a{};
+    a.lv = c->lv_dev;
+    a.parity = parity;
+    int b = 0;
+    for (int s = 0; s < c->S; ++s) {
+        const StreamInfo& si = c->st[s];
+        if (level >= si.H) continue;
+        const int e = si.e0 + level;
+        a.ent[a.n] = e;
+        a.blk[a.n] = b;
+        b += (c->lv[e].rows * c->lv[e].cols + kElemBlock - 1) / kElemBlock;
+        ++a.n;
+    }
+    a.blk[a.n] = b;
+    return a;
 }
 
 extern "C" {
 
-sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out) {
+sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf_ctx* out) {
     if (!out) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL output pointer");
     *out = nullptr;
-    sf_config c;
-    sf_status st = validate_config(cfg, &c);
-    if (st != SF_OK) return st;
+    if (!cfgs) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL config");
+    if (n < 1 || n > kMaxStreams)
+        return fail(nullptr, SF_ERR_INVALID_ARG, "stream count must be in [1, %d]", kMaxStreams);
+    std::vector<sf_config> cf(n);
+    for (int s = 0; s < n; ++s) {
+        sf_status st = validate_config(&cfgs[s], &cf[s]);
+        if (st != SF_OK) {
+            if (n > 1) g_create_error = "stream " + std::to_string(s) + ": " + g_create_error;
+            return st;
+        }
+        if (cf[s].storage != cf[0].storage)
+            return fail(nullptr, SF_ERR_INVALID_ARG, "all streams of a batch need the same storage");
+        if (cf[s].update != cf[0].update)
+            return fail(nullptr, SF_ERR_INVALID_ARG, "all streams of a batch need the same update");
+    }
     sf_ctx ctx = new (std::nothrow) sf_ctx_s();
     if (!ctx) return fail(nullptr, SF_ERR_OOM, "host allocation failed");
-    ctx->cfg = c;
+    ctx->S = n;
+    ctx->storage = cf[0].storage;
     ctx->stream = (hipStream_t)hip_stream;
-    ctx->H = c.levels;
-    ctx->esize = c.storage == SF_FP16 ? 2 : 4;
-    // sizes and pitches
-    size_t total = 0;
+    ctx->esize = ctx->storage == SF_FP16 ? 2 : 4;
+    ctx->st.resize(n);
     const size_t align = 256;
     auto plane_bytes = [&](int rows, int pitch) {
         return ((size_t)rows * pitch * ctx->esize + align - 1) / align * align;
     };
-    int r = c.rows, q = c.cols;
-    for (int h = 0; h < ctx->H; ++h) {
-        LevelDev& L = ctx->lv[h];
-        L.rows = r;
-        L.cols = q;
-        const int per_row = (int)(align / ctx->esize);
-        L.pitch = (q + per_row - 1) / per_row * per_row;
-        L.top = h == ctx->H - 1;
-        const int nplanes = 2 * (3 + (L.top ? 0 : 3) + 2) + (h > 0 ? 2 : 0);
-        total += nplanes * plane_bytes(r, L.pitch);
-        r = (r + 1) / 2;
-        q = (q + 1) / 2;
+    size_t total = 0;
+    for (int s = 0; s < n; ++s) {
+        StreamInfo& si = ctx->st[s];
+        si.cfg = cf[s];
+        si.H = cf[s].levels;
+        si.e0 = (int)ctx->lv.size();
+        ctx->max_levels = std::max(ctx->max_levels, si.H);
+        int r = cf[s].rows, q = cf[s].cols;
+        for (int h = 0; h < si.H; ++h) {
+            LevelDev L{};
+            L.rows = r;
+            L.cols = q;
+            const int per_row = (int)(align / ctx->esize);
+            L.pitch = (q + per_row - 1) / per_row * per_row;
+            L.top = h == si.H - 1;
+            L.stream = s;
+            L.level = h;
+            L.child = h > 0 ? si.e0 + h - 1 : -1;
+            L.parent = h + 1 < si.H ? si.e0 + h + 1 : -1;
+            L.flags = cf[s].read_flags;
+            const int nplanes = 2 * (3 + (L.top ? 0 : 3) + 2) + (h > 0 ? 2 : 0);
+            total += nplanes * plane_bytes(r, L.pitch);
+            ctx->lv.push_back(L);
+            r = (r + 1) / 2;
+            q = (q + 1) / 2;
+        }
     }
-    total += align + sizeof(LevelDev) * kMaxLevels;
+    total += align + sizeof(LevelDev) * ctx->lv.size();
     hipError_t e = hipMalloc((void**)&ctx->arena, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -218,9 +283,8 @@ sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out) {
     }
     ctx->arena_bytes = total;
     char* p = ctx->arena;
-    auto take = [&](size_t n) { char* x = p; p += n; return (void*)x; };
-    for (int h = 0; h < ctx->H; ++h) {
-        LevelDev& L = ctx->lv[h];
+    auto take = [&](size_t nb) { char* x = p; p += nb; return (void*)x; };
+    for (auto& L : ctx->lv) {
         const size_t pb = plane_bytes(L.rows, L.pitch);
         for (int par = 0; par < 2; ++par) {
             for (int k = 0; k < 3; ++k) L.w[par][k] = take(pb);
@@ -228,10 +292,63 @@ sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out) {
             L.rho[par] = take(pb);
             L.Y[par] = take(pb);
         }
-        L.Ym = h > 0 ? take(pb) : nullptr;
-        L.Rm = h > 0 ? take(pb) : nullptr;
+        L.Ym = L.level > 0 ? take(pb) : nullptr;
+        L.Rm = L.level > 0 ? take(pb) : nullptr;
     }
-    ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * kMaxLevels);
+    ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * ctx->lv.size());
+    if (cf[0].update == SF_UPDATE_LEARNED) {
+        ctx->learned = true;
+        CnnSegs& sg = ctx->segs;
+        sg.n = n;
+        int b = 0;
+        int o = 0;
+        for (int s = 0; s < n; ++s) {
+            sg.base[s] = b;
+            sg.off[s] = o;
+            sg.rows[s] = cf[s].rows;
+            sg.cols[s] = cf[s].cols;
+            b += (cf[s].rows * cf[s].cols + 15) / 16 * 16;
+            o += cf[s].rows * cf[s].cols;
+        }
+        sg.base[n] = b;
+        sg.off[n] = o;
+        sg.total = b;
+        size_t lb_bytes = (size_t)kLearnPlanes * b * sizeof(float);
+        size_t act_bytes = (size_t)b * 16 * sizeof(uint16_t);
+        size_t need = lb_bytes + 2 * act_bytes + 2 * 4 * 9 * 256 * sizeof(uint16_t) +
+                      4 * 16 * sizeof(float) + kCnnParams * sizeof(float) + 64 + 6 * 256;
+        hipError_t e2 = hipMalloc((void**)&ctx->lbuf, need);
+        if (e2 != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(ctx->arena);
+            delete ctx;
+            return fail(nullptr, e2 == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                        "hipMalloc of the learned buffers failed: %s", hipGetErrorString(e2));
+        }
+        auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+        char* q = (char*)ctx->lbuf + al(lb_bytes);
+        ctx->act[0] = (uint16_t*)q; q += al(act_bytes);
+        ctx->act[1] = (uint16_t*)q; q += al(act_bytes);
+        ctx->wf = (uint16_t*)q; q += al(4 * 9 * 256 * sizeof(uint16_t));
+        ctx->wb = (uint16_t*)q; q += al(4 * 9 * 256 * sizeof(uint16_t));
+        ctx->cnn_bias = (float*)q; q += al(4 * 16 * sizeof(float));
+        ctx->params_dev = (float*)q; q += al(kCnnParams * sizeof(float));
+        ctx->fallbacks = (unsigned long long*)q;
+        for (int s = 0; s < n; ++s) {
+            LevelDev& L = ctx->lv[ctx->st[s].e0];
+            L.learned = 1;
+            L.lbase = sg.base[s];
+            L.ltotal = b;
+            L.lbuf = ctx->lbuf;
+        }
+        e2 = hipMemsetAsync(ctx->lbuf, 0, need, ctx->stream);
+        if (e2 != hipSuccess) {
+            (void)hipFree(ctx->lbuf);
+            (void)hipFree(ctx->arena);
+            delete ctx;
+            return fail(nullptr, SF_ERR_HIP, "clearing the learned buffers failed");
+        }
+    }
     e = hipMemsetAsync(ctx->arena, 0, total, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
@@ -243,63 +360,94 @@ sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out) {
     return SF_OK;
 }
 
+sf_status sf_create(const sf_config* cfg, void* hip_stream, sf_ctx* out) {
+    return sf_create_batch(cfg, 1, hip_stream, out);
+}
+
+sf_status sf_stream_count(sf_ctx c, int32_t* n) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!n) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
+    *n = c->S;
+    return SF_OK;
+}
+
 static sf_status upload_levels(sf_ctx c) {
     layout_blocks(c);
-    HIP_TRY(c, prepare_kernels(std::max<size_t>(c->lds_bytes, 65536)));
-    HIP_TRY(c, hipMemcpyAsync(c->lv_dev, c->lv, sizeof(LevelDev) * kMaxLevels,
+    HIP_TRY(c, prepare_kernels(c->lds_bytes));
+    HIP_TRY(c, hipMemcpyAsync(c->lv_dev, c->lv.data(), sizeof(LevelDev) * c->lv.size(),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SF_OK;
 }
 
-sf_status sf_set_camera(sf_ctx c, const sf_camera* cam) {
+sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
-    if (!cam) return fail(c, SF_ERR_INVALID_ARG, "NULL camera");
-    if (!(cam->fx > 0) || !(cam->fy > 0) || !isfinite(cam->fx) || !isfinite(cam->fy) ||
-        !isfinite(cam->cx) || !isfinite(cam->cy))
-        return fail(c, SF_ERR_INVALID_ARG, "fx, fy must be finite and > 0, cx, cy finite");
-    c->cam[0] = cam->fx; c->cam[1] = cam->fy; c->cam[2] = cam->cx; c->cam[3] = cam->cy;
-    const sf_config& cf = c->cfg;
-    for (int h = 0; h < c->H; ++h) {
-        LevelDev& L = c->lv[h];
-        const double s = ldexp(1.0, h);
-        const double fx = cam->fx / s, fy = cam->fy / s, cx = cam->cx / s, cy = cam->cy / s;
-        L.ifx = (float)(1.0 / fx);
-        L.ify = (float)(1.0 / fy);
-        L.cxn = (float)(cx / fx);
-        L.cyn = (float)(cy / fy);
-        L.fx = (float)fx;
-        L.N = level_steps(cf.max_flow_px, h);
-        L.Ns = cf.smooth_iters[h];
-        L.halo = level_halo(L.N, L.Ns);
-        const double dmu0 = 1.0 / sqrt(fx * fx + 1.0);
-        L.g1 = (float)(cf.alpha[0] / (dmu0 * dmu0));
-        L.g2 = (float)(cf.alpha[1] / (dmu0 * dmu0));
-        L.g3 = cf.alpha[2];
-        L.g4 = cf.alpha[3];
-        L.g5 = cf.alpha[4];
-        L.qscale = (float)(1.0 / dmu0);   // half storage keeps flow in pixels per frame
+    if (!cams) return fail(c, SF_ERR_INVALID_ARG, "NULL camera");
+    for (int s = 0; s < c->S; ++s) {
+        const sf_camera* cam = &cams[s];
+        if (!(cam->fx > 0) || !(cam->fy > 0) || !isfinite(cam->fx) || !isfinite(cam->fy) ||
+            !isfinite(cam->cx) || !isfinite(cam->cy))
+            return fail(c, SF_ERR_INVALID_ARG,
+                        "camera %d: fx, fy must be finite and > 0, cx, cy finite", s);
+    }
+    for (int s = 0; s < c->S; ++s) {
+        StreamInfo& si = c->st[s];
+        const sf_camera* cam = &cams[s];
+        si.cam[0] = cam->fx; si.cam[1] = cam->fy; si.cam[2] = cam->cx; si.cam[3] = cam->cy;
+        const sf_config& cf = si.cfg;
+        for (int h = 0; h < si.H; ++h) {
+            LevelDev& L = c->lv[si.e0 + h];
+            const double sc = ldexp(1.0, h);
+            const double fx = cam->fx / sc, fy = cam->fy / sc, cx = cam->cx / sc, cy = cam->cy / sc;
+            L.ifx = (float)(1.0 / fx);
+            L.ify = (float)(1.0 / fy);
+            L.cxn = (float)(cx / fx);
+            L.cyn = (float)(cy / fy);
+            L.fx = (float)fx;
+            L.N = level_steps(cf.max_flow_px, h);
+            L.Ns = cf.smooth_iters[h];
+            L.halo = level_halo(L.N, L.Ns);
+            const double dmu0 = 1.0 / sqrt(fx * fx + 1.0);
+            L.g1 = (float)(cf.alpha[0] / (dmu0 * dmu0));
+            L.g2 = (float)(cf.alpha[1] / (dmu0 * dmu0));
+            L.g3 = cf.alpha[2];
+            L.g4 = cf.alpha[3];
+            L.g5 = cf.alpha[4];
+            L.qscale = (float)(1.0 / dmu0);   // half storage keeps flow in pixels per frame
+        }
+        si.dt_prev = 0.0;
     }
     sf_status s2 = upload_levels(c);
     if (s2 != SF_OK) return s2;
     c->camera = true;
     c->frames = 0;
     c->parity = 0;
-    c->dt_prev = 0.0;
     return SF_OK;
+}
+
+sf_status sf_set_camera(sf_ctx c, const sf_camera* cam) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_set_cameras");
+    return sf_set_cameras(c, cam);
 }
 
 sf_status sf_set_tile(sf_ctx c, int32_t level, int32_t tw, int32_t th) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
-    if (level < 1 || level > c->H) return fail(c, SF_ERR_INVALID_ARG, "level out of range");
+    if (level < 1 || level > c->max_levels) return fail(c, SF_ERR_INVALID_ARG, "level out of range");
     const int h = level - 1;
     if (!(tw == 0 && th == 0)) {
-        const int halo = level_halo(level_steps(c->cfg.max_flow_px, h), c->cfg.smooth_iters[h]);
-        if (tw < 1 || th < 1 || tw + 2 * halo > kRegion || th + 2 * halo > kRegion)
-            return fail(c, SF_ERR_INVALID_ARG, "tile %dx%d with halo %d exceeds %d", tw, th, halo,
-                        kRegion);
+        for (int s = 0; s < c->S; ++s) {
+            const StreamInfo& si = c->st[s];
+            if (h >= si.H) continue;
+            const int halo = level_halo(level_steps(si.cfg.max_flow_px, h), si.cfg.smooth_iters[h]);
+            if (tw < 1 || th < 1 || tw + 2 * halo > kRegion || th + 2 * halo > kRegion)
+                return fail(c, SF_ERR_INVALID_ARG, "tile %dx%d with halo %d exceeds %d", tw, th,
+                            halo, kRegion);
+        }
     }
     c->user_tw[h] = tw;
     c->user_th[h] = th;
@@ -368,75 +516,230 @@ sf_status sf_kernel_times(sf_ctx c, double* ms3, int64_t* launches3, int32_t res
     return SF_OK;
 }
 
+// -- learned update -------------------------------------------------------------------------
+static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias) {
+    PackArgs p{};
+    p.params = params;
+    static const int ch[5] = {6, 16, 16, 16, 3};
+    int off = 0;
+    for (int l = 0; l < kCnnLayers; ++l) {
+        p.cin[l] = ch[l];
+        p.cout[l] = ch[l + 1];
+        p.woff[l] = off;
+        off += 9 * ch[l] * ch[l + 1];
+        p.boff[l] = off;
+        off += ch[l + 1];
+    }
+    p.wf = wf;
+    p.wb = wb;
+    p.bias = bias;
+    return p;
+}
+
+// network on the finest level of every stream, then the per-pixel choice, smoothing and store
+static sf_status run_learned(sf_ctx c, int q) {
+    const int P = c->segs.total;
+    HIP_TRY(c, launch_pack_inputs(c->lbuf + (size_t)kLearnIn * P, 6, P, c->act[0], c->stream));
+    for (int l = 0; l < kCnnLayers; ++l) {
+        ConvArgs a{};
+        a.segs = c->segs;
+        a.in = c->act[l & 1];
+        a.w = c->wf + (size_t)l * 9 * 256;
+        a.bias = c->cnn_bias + l * 16;
+        a.relu = l < kCnnLayers - 1;
+        a.nout = l < kCnnLayers - 1 ? 16 : 3;
+        a.out = c->act[(l + 1) & 1];
+        a.out_f32 = c->lbuf + (size_t)kLearnOut * P;
+        HIP_TRY(c, launch_conv(a, l == kCnnLayers - 1, c->stream));
+    }
+    CombineArgs cb{};
+    cb.lv = c->lv_dev;
+    cb.parity = q;
+    cb.threshold = c->threshold;
+    cb.fallbacks = c->fallbacks;
+    int b = 0;
+    for (int s = 0; s < c->S; ++s) {
+        const LevelDev& L = c->lv[c->st[s].e0];
+        cb.ent[cb.n] = c->st[s].e0;
+        cb.blk[cb.n] = b;
+        b += ((L.rows + 31) / 32) * ((L.cols + 31) / 32);
+        ++cb.n;
+        c->learned_pixels += (int64_t)L.rows * L.cols;
+    }
+    cb.blk[cb.n] = b;
+    HIP_TRY(c, launch_combine(c->storage, cb, c->stream));
+    return SF_OK;
+}
+
+sf_status sf_set_learned(sf_ctx c, const float* params, size_t n, float threshold) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!c->learned) return fail(c, SF_ERR_STATE, "the context was not created with the learned update");
+    if (!params) return fail(c, SF_ERR_INVALID_ARG, "NULL parameters");
+    if (n != (size_t)kCnnParams) return fail(c, SF_ERR_INVALID_ARG, "expected %d parameters", kCnnParams);
+    if (isnan(threshold)) return fail(c, SF_ERR_INVALID_ARG, "threshold must not be NaN");
+    for (size_t k = 0; k < n; ++k)
+        if (!isfinite(params[k])) return fail(c, SF_ERR_INVALID_ARG, "parameters must be finite");
+    HIP_TRY(c, hipMemcpyAsync(c->params_dev, params, n * sizeof(float), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, launch_pack_weights(pack_args(c->params_dev, c->wf, c->wb, c->cnn_bias), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->threshold = threshold;
+    c->weights = true;
+    return SF_OK;
+}
+
+sf_status sf_learned_stats(sf_ctx c, int64_t* fallbacks, int64_t* pixels, int32_t reset) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!fallbacks || !pixels) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
+    if (!c->learned) return fail(c, SF_ERR_STATE, "not a learned context");
+    unsigned long long v = 0;
+    HIP_TRY(c, hipMemcpyAsync(&v, c->fallbacks, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *fallbacks = (int64_t)v;
+    *pixels = c->learned_pixels;
+    if (reset) {
+        HIP_TRY(c, hipMemsetAsync(c->fallbacks, 0, sizeof v, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->learned_pixels = 0;
+    }
+    return SF_OK;
+}
+
+sf_status sf_get_update_inputs(sf_ctx c, int32_t stream, float* out) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!c->learned) return fail(c, SF_ERR_STATE, "not a learned context");
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
+    if (c->frames < 2) return fail(c, SF_ERR_STATE, "no update has run yet");
+    ElemArgs a{};
+    a.lv = c->lv_dev;
+    a.n = 1;
+    a.ent[0] = c->st[stream].e0;
+    a.blk[0] = 0;
+    const LevelDev& L = c->lv[a.ent[0]];
+    a.blk[1] = (L.rows * L.cols + kElemBlock - 1) / kElemBlock;
+    a.parity = c->parity;
+    a.out = out;
+    HIP_TRY(c, launch_learned_extract(c->storage, a, c->stream));
+    return SF_OK;
+}
+
 // -- frames ---------------------------------------------------------------------------------
-static sf_status run_pyramid(sf_ctx c, const void* Y, const void* rho) {
-    for (int h = 0; h + 1 < c->H; ++h) {
-        const void* ys = h == 0 ? Y : c->lv[h].Ym;
-        const void* rs = h == 0 ? rho : c->lv[h].Rm;
-        const int sp = h == 0 ? c->lv[0].cols : c->lv[h].pitch;
+sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho, const double* dt) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!c->camera) return fail(c, SF_ERR_STATE, "the cameras must be set before pushing");
+    if (c->learned && !c->weights)
+        return fail(c, SF_ERR_STATE, "the learned update needs sf_set_learned before pushing");
+    if (!Y || !rho || !dt) return fail(c, SF_ERR_INVALID_ARG, "NULL argument array");
+    for (int s = 0; s < c->S; ++s) {
+        if (!is_device_ptr(Y[s]) || !is_device_ptr(rho[s]))
+            return fail(c, SF_ERR_INVALID_ARG, "stream %d: Y and rho must be device pointers", s);
+        if (!(dt[s] > 0.0) || !isfinite(dt[s]))
+            return fail(c, SF_ERR_INVALID_ARG, "stream %d: dt must be > 0 and finite", s);
+    }
+    FrameInputs in{};
+    for (int s = 0; s < c->S; ++s) {
+        in.Y[s] = Y[s];
+        in.R[s] = rho[s];
+        const double dp = c->st[s].dt_prev;
+        in.scale[s] = (c->frames == 0 || dt[s] == dp) ? 1.0f : (float)(dt[s] / dp);
+    }
+    // pyramid, finest to coarsest
+    for (int h = 1; h < c->max_levels; ++h) {
+        ElemArgs a = elem_args(c, h, 0);
+        a.in = in;
         TimedLaunch t(c, 0);
-        HIP_TRY(c, launch_pyramid(c->cfg.storage, c->lv, c->lv_dev, h, ys, rs, sp, c->stream));
+        HIP_TRY(c, launch_pyramid(c->storage, a, c->stream));
         t.done();
     }
+    if (c->frames == 0) {
+        for (int h = 0; h < c->max_levels; ++h) {
+            ElemArgs a = elem_args(c, h, 0);
+            a.in = in;
+            HIP_TRY(c, launch_init(c->storage, a, c->stream));
+        }
+        c->parity = 0;
+    } else {
+        StepArgs a{};
+        a.lv = c->lv_dev;
+        a.nent = (int)c->lv.size();
+        a.parity = c->parity;
+        a.in = in;
+        {
+            TimedLaunch t(c, 1);
+            HIP_TRY(c, launch_step(c->storage, a, c->nblocks, c->lds_bytes, c->stream));
+            t.done();
+        }
+        const int q = 1 - c->parity;
+        if (c->learned) {
+            sf_status s2 = run_learned(c, q);
+            if (s2 != SF_OK) return s2;
+        }
+        for (int h = c->max_levels - 2; h >= 0; --h) {
+            // reconstruction of level h for the streams where h is below the top
+            ElemArgs r{};
+            r.lv = c->lv_dev;
+            r.parity = q;
+            int b = 0;
+            for (int s = 0; s < c->S; ++s) {
+                const StreamInfo& si = c->st[s];
+                if (h >= si.H - 1) continue;
+                const int e = si.e0 + h;
+                r.ent[r.n] = e;
+                r.blk[r.n] = b;
+                b += (c->lv[e].rows * c->lv[e].cols + kElemBlock - 1) / kElemBlock;
+                ++r.n;
+            }
+            r.blk[r.n] = b;
+            TimedLaunch t(c, 2);
+            HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
+            t.done();
+        }
+        c->parity = q;
+    }
+    for (int s = 0; s < c->S; ++s) c->st[s].dt_prev = dt[s];
+    c->frames += 1;
     return SF_OK;
 }
 
 sf_status sf_push_frame(sf_ctx c, const void* Y, const void* rho, double dt) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
-    if (!c->camera) return fail(c, SF_ERR_STATE, "sf_set_camera must be called before pushing");
-    if (!is_device_ptr(Y) || !is_device_ptr(rho))
-        return fail(c, SF_ERR_INVALID_ARG, "Y and rho must be device pointers");
-    if (!(dt > 0.0) || !isfinite(dt)) return fail(c, SF_ERR_INVALID_ARG, "dt must be > 0 and finite");
-    st = run_pyramid(c, Y, rho);
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_push_frames");
+    return sf_push_frames(c, &Y, &rho, &dt);
+}
+
+sf_status sf_get_flow_stream(sf_ctx c, int32_t stream, int32_t kind, void* out) {
+    sf_status st = check_alive(c);
     if (st != SF_OK) return st;
-    if (c->frames == 0) {
-        for (int h = 0; h < c->H; ++h) {
-            const void* ym = h == 0 ? Y : c->lv[h].Ym;
-            const void* rm = h == 0 ? rho : c->lv[h].Rm;
-            const int mp = h == 0 ? c->lv[0].cols : c->lv[h].pitch;
-            HIP_TRY(c, launch_init(c->cfg.storage, c->lv, c->lv_dev, h, ym, rm, mp, c->stream));
-        }
-        c->parity = 0;
-        c->frames = 1;
-        c->dt_prev = dt;
-        return SF_OK;
-    }
-    StepArgs a;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    if (kind < SF_FLOW_W_RAD_S || kind > SF_FLOW_W_FRAME)
+        return fail(c, SF_ERR_INVALID_ARG, "unknown flow kind %d", kind);
+    if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
+    if (!c->camera || c->frames == 0) return fail(c, SF_ERR_STATE, "no frame has been pushed");
+    ElemArgs a{};
     a.lv = c->lv_dev;
-    a.nlev = c->H;
-    a.Y1 = Y;
-    a.R1 = rho;
+    a.n = 1;
+    a.ent[0] = c->st[stream].e0;
+    a.blk[0] = 0;
+    a.blk[1] = (c->lv[a.ent[0]].rows * c->lv[a.ent[0]].cols + kElemBlock - 1) / kElemBlock;
     a.parity = c->parity;
-    a.scale = dt == c->dt_prev ? 1.0f : (float)(dt / c->dt_prev);
-    a.flags = c->cfg.read_flags;
-    {
-        TimedLaunch t(c, 1);
-        HIP_TRY(c, launch_step(c->cfg.storage, a, c->nblocks, c->lds_bytes, c->stream));
-        t.done();
-    }
-    const int q = 1 - c->parity;
-    for (int h = c->H - 2; h >= 0; --h) {
-        TimedLaunch t(c, 2);
-        HIP_TRY(c, launch_reconstruct(c->cfg.storage, c->lv, c->lv_dev, h, q, c->stream));
-        t.done();
-    }
-    c->parity = q;
-    c->frames += 1;
-    c->dt_prev = dt;
+    a.kind = kind;
+    a.inv_dt = (float)(1.0 / c->st[stream].dt_prev);
+    a.out = (float*)out;
+    HIP_TRY(c, launch_output(c->storage, a, c->stream));
     return SF_OK;
 }
 
 sf_status sf_get_flow(sf_ctx c, int32_t kind, void* out) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
-    if (kind < SF_FLOW_W_RAD_S || kind > SF_FLOW_W_FRAME)
-        return fail(c, SF_ERR_INVALID_ARG, "unknown flow kind %d", kind);
-    if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
-    if (!c->camera || c->frames == 0) return fail(c, SF_ERR_STATE, "no frame has been pushed");
-    HIP_TRY(c, launch_output(c->cfg.storage, c->lv, c->lv_dev, c->parity, kind,
-                             (float)(1.0 / c->dt_prev), (float*)out, c->stream));
-    return SF_OK;
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_get_flow_stream");
+    return sf_get_flow_stream(c, 0, kind, out);
 }
 
 // -- state blob -----------------------------------------------------------------------------
@@ -451,21 +754,14 @@ struct BlobHeader {
 static_assert(sizeof(BlobHeader) == 32, "blob header is 32 bytes");
 static const uint32_t kMagic = 0x54535346u;   // 'SFST'
 
-static size_t blob_bytes(sf_ctx c) {
+static size_t blob_bytes(sf_ctx c, int s) {
     size_t n = sizeof(BlobHeader);
-    for (int h = 0; h < c->H; ++h) {
-        const LevelDev& L = c->lv[h];
+    const StreamInfo& si = c->st[s];
+    for (int h = 0; h < si.H; ++h) {
+        const LevelDev& L = c->lv[si.e0 + h];
         n += (size_t)(L.top ? 5 : 8) * L.rows * L.cols * sizeof(float);
     }
     return n;
-}
-
-sf_status sf_state_size(sf_ctx c, size_t* bytes) {
-    sf_status st = check_alive(c);
-    if (st != SF_OK) return st;
-    if (!bytes) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
-    *bytes = blob_bytes(c);
-    return SF_OK;
 }
 
 static float half_to_float(uint16_t h) {
@@ -549,10 +845,11 @@ static sf_status copy_plane(sf_ctx c, bool to_host, void* dev, int pitch, int ro
     return SF_OK;
 }
 
-static sf_status transfer_state(sf_ctx c, bool to_host, float* f) {
+static sf_status transfer_state(sf_ctx c, int s, bool to_host, float* f) {
     std::vector<uint16_t> scratch;
-    for (int h = 0; h < c->H; ++h) {
-        LevelDev& L = c->lv[h];
+    const StreamInfo& si = c->st[s];
+    for (int h = 0; h < si.H; ++h) {
+        LevelDev& L = c->lv[si.e0 + h];
         const size_t n = (size_t)L.rows * L.cols;
         const float fin = c->esize == 2 ? 1.0f / L.qscale : 1.0f;    // stored -> rad/frame
         const float mul = to_host ? fin : 1.0f / fin;
@@ -577,34 +874,51 @@ static sf_status transfer_state(sf_ctx c, bool to_host, float* f) {
     return SF_OK;
 }
 
-sf_status sf_get_state(sf_ctx c, void* host_blob, size_t bytes) {
+sf_status sf_state_size_stream(sf_ctx c, int32_t stream, size_t* bytes) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
+    if (!bytes) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    *bytes = blob_bytes(c, stream);
+    return SF_OK;
+}
+
+sf_status sf_get_state_stream(sf_ctx c, int32_t stream, void* host_blob, size_t bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
     if (!host_blob) return fail(c, SF_ERR_INVALID_ARG, "NULL blob");
-    if (bytes != blob_bytes(c)) return fail(c, SF_ERR_INVALID_ARG, "blob must be %zu bytes", blob_bytes(c));
+    if (bytes != blob_bytes(c, stream))
+        return fail(c, SF_ERR_INVALID_ARG, "blob must be %zu bytes", blob_bytes(c, stream));
     if (!c->camera) return fail(c, SF_ERR_STATE, "no camera set");
-    BlobHeader hd{kMagic, 1u, c->H, c->frames > 0 ? 1 : 0, c->dt_prev, c->frames};
+    const StreamInfo& si = c->st[stream];
+    BlobHeader hd{kMagic, 1u, si.H, c->frames > 0 ? 1 : 0, si.dt_prev, c->frames};
     memcpy(host_blob, &hd, sizeof hd);
     if (c->frames == 0) {
         memset((char*)host_blob + sizeof hd, 0, bytes - sizeof hd);
         return SF_OK;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return transfer_state(c, true, (float*)((char*)host_blob + sizeof hd));
+    return transfer_state(c, stream, true, (float*)((char*)host_blob + sizeof hd));
 }
 
-sf_status sf_set_state(sf_ctx c, const void* host_blob, size_t bytes) {
+sf_status sf_set_state_stream(sf_ctx c, int32_t stream, const void* host_blob, size_t bytes) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
     if (!host_blob) return fail(c, SF_ERR_INVALID_ARG, "NULL blob");
-    if (bytes != blob_bytes(c)) return fail(c, SF_ERR_INVALID_ARG, "blob must be %zu bytes", blob_bytes(c));
+    if (bytes != blob_bytes(c, stream))
+        return fail(c, SF_ERR_INVALID_ARG, "blob must be %zu bytes", blob_bytes(c, stream));
     if (!c->camera) return fail(c, SF_ERR_STATE, "no camera set");
     BlobHeader hd;
     memcpy(&hd, host_blob, sizeof hd);
-    if (hd.magic != kMagic || hd.version != 1u || hd.levels != c->H)
-        return fail(c, SF_ERR_INVALID_ARG, "blob header does not match this context");
+    StreamInfo& si = c->st[stream];
+    if (hd.magic != kMagic || hd.version != 1u || hd.levels != si.H)
+        return fail(c, SF_ERR_INVALID_ARG, "blob header does not match this stream");
     if (hd.initialised && !(hd.dt_prev > 0.0 && isfinite(hd.dt_prev)))
         return fail(c, SF_ERR_INVALID_ARG, "blob dt_prev must be > 0");
+    if (c->S > 1 && (!hd.initialised || c->frames == 0))
+        return fail(c, SF_ERR_STATE, "a batch takes states only once every stream has a frame");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (!hd.initialised) {
         c->frames = 0;
@@ -613,12 +927,32 @@ sf_status sf_set_state(sf_ctx c, const void* host_blob, size_t bytes) {
     }
     std::vector<float> tmp((bytes - sizeof hd) / sizeof(float));
     memcpy(tmp.data(), (const char*)host_blob + sizeof hd, bytes - sizeof hd);
-    c->parity = 0;
-    sf_status s = transfer_state(c, false, tmp.data());
-    if (s != SF_OK) return s;
-    c->frames = std::max<int64_t>(1, hd.frames);
-    c->dt_prev = hd.dt_prev;
+    sf_status s2 = transfer_state(c, stream, false, tmp.data());
+    if (s2 != SF_OK) return s2;
+    if (c->S == 1) c->frames = std::max<int64_t>(1, hd.frames);
+    si.dt_prev = hd.dt_prev;
     return SF_OK;
+}
+
+sf_status sf_state_size(sf_ctx c, size_t* bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_state_size_stream");
+    return sf_state_size_stream(c, 0, bytes);
+}
+
+sf_status sf_get_state(sf_ctx c, void* host_blob, size_t bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_get_state_stream");
+    return sf_get_state_stream(c, 0, host_blob, bytes);
+}
+
+sf_status sf_set_state(sf_ctx c, const void* host_blob, size_t bytes) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_set_state_stream");
+    return sf_set_state_stream(c, 0, host_blob, bytes);
 }
 
 sf_status sf_destroy(sf_ctx c) {
@@ -627,6 +961,7 @@ sf_status sf_destroy(sf_ctx c) {
     for (auto& m : c->marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->arena) (void)hipFree(c->arena);
+    if (c->lbuf) (void)hipFree(c->lbuf);
     delete c;
     return SF_OK;
 }

@@ -1,0 +1,349 @@
+// The learned update's network on gfx950: a 4-layer 3x3 convolutional network
+// (6 -> 16 -> 16 -> 16 -> 3 channels, ReLU after the first three layers, zero padding) in
+// BF16 on the matrix cores with FP32 accumulation, and the kernels that train it.
+//
+// Activations are NHWC with 16 BF16 channels per pixel (32 bytes; unused channels are 0),
+// for a list of images stored one after the other ("segments"), each image's pixel range
+// padded to a multiple of 16 so that a wave's 16 pixels never straddle two images.
+//
+// Convolution as an implicit GEMM: a wave computes a 16-pixel x 16-output-channel tile with
+// nine v_mfma_f32_16x16x16_bf16 (one per tap, K = 16 input channels).  Operand layout of
+// that instruction (64 lanes): lane l holds A[l%16][4(l/16) .. +3] and B[4(l/16) .. +3][l%16]
+// and receives D[4(l/16) .. +3][l%16].  Here A[i][k] = input channel k of pixel i shifted by
+// the tap, B[k][j] = weight (tap, k -> j), D[i][j] = output channel j of pixel i.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sflow_cnn.h"
+
+namespace sflow {
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t v) {
+    return __builtin_bit_cast(float, (uint32_t)v << 16);
+}
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// the image a 16-pixel group belongs to
+__device__ __forceinline__ int find_seg(const CnnSegs& s, int p) {
+    int k = 0;
+    while (k + 1 < s.n && s.base[k + 1] <= p) ++k;
+    return k;
+}
+
+// A operand for tap (dy, dx): four input channels of the lane's pixel, shifted; 0 outside
+// the image.  If `mask` is set the values are kept only where mask > 0 (ReLU derivative).
+__device__ __forceinline__ s4 load_a(const uint16_t* in, const uint16_t* mask, int base, int rows,
+                                     int cols, int y, int x, int dy, int dx, int c0, bool valid) {
+    s4 a = {0, 0, 0, 0};
+    const int yy = y + dy, xx = x + dx;
+    if (valid && yy >= 0 && yy < rows && xx >= 0 && xx < cols) {
+        const size_t off = ((size_t)base + (size_t)yy * cols + xx) * 16 + c0;
+        const uint2 v = *(const uint2*)(in + off);
+        a[0] = (short)(v.x & 0xffff);
+        a[1] = (short)(v.x >> 16);
+        a[2] = (short)(v.y & 0xffff);
+        a[3] = (short)(v.y >> 16);
+        if (mask) {
+            const uint2 m = *(const uint2*)(mask + off);
+            if (bf2f((uint16_t)(m.x & 0xffff)) <= 0.0f) a[0] = 0;
+            if (bf2f((uint16_t)(m.x >> 16)) <= 0.0f) a[1] = 0;
+            if (bf2f((uint16_t)(m.y & 0xffff)) <= 0.0f) a[2] = 0;
+            if (bf2f((uint16_t)(m.y >> 16)) <= 0.0f) a[3] = 0;
+        }
+    }
+    return a;
+}
+
+// 3x3 convolution layer over all segments.  One wave per 16 pixels.
+template <bool OUT_F32>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int g = (blockIdx.x * 256 + threadIdx.x) >> 6;     // 16-pixel group
+    const int p0 = g * 16;
+    if (p0 >= a.segs.total) return;                          // whole wave exits together
+    const int sgi = find_seg(a.segs, p0);
+    const int base = a.segs.base[sgi], rows = a.segs.rows[sgi], cols = a.segs.cols[sgi];
+    const int npx = rows * cols;
+    // A-operand pixel of this lane
+    const int ia = p0 - base + (lane & 15);
+    const bool va = ia < npx;
+    const int ya = va ? ia / cols : 0, xa = va ? ia - ya * cols : 0;
+    const int c0 = 4 * (lane >> 4);
+    f4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const s4 av = load_a(a.in, a.mask, base, rows, cols, ya, xa, dy, dx, c0, va);
+        // B: weight[tap t][out j = lane%16][in 4(lane/16)..+3]
+        const uint2 wv = *(const uint2*)(a.w + ((size_t)t * 16 + (lane & 15)) * 16 + c0);
+        s4 bv;
+        bv[0] = (short)(wv.x & 0xffff);
+        bv[1] = (short)(wv.x >> 16);
+        bv[2] = (short)(wv.y & 0xffff);
+        bv[3] = (short)(wv.y >> 16);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    const int j = lane & 15;
+    const float bias = a.bias ? a.bias[j] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = p0 - base + 4 * (lane >> 4) + r;
+        if (i >= npx) continue;
+        float v = acc[r] + bias;
+        if (a.relu) v = fmaxf(v, 0.0f);
+        if (OUT_F32) {
+            if (j < a.nout) a.out_f32[(size_t)j * a.segs.total + base + i] = v;
+        } else {
+            a.out[((size_t)base + i) * 16 + j] = j < a.nout ? f2bf(v) : (uint16_t)0;
+        }
+    }
+}
+
+// Weight and bias gradients of one layer: dW[t][c][n] = sum_p in[p + t][c] g[p][n],
+// db[n] = sum_p g[p][n], with g = dout masked by (act > 0) when act is given.  Each wave
+// reduces `per_wave` 16-pixel groups on the matrix cores and adds its partial sums to the
+// FP32 gradient (A = input channels x pixels, B = pixels x output channels).
+__global__ void __launch_bounds__(256) k_conv_dw(DwArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wv = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int g0 = wv * a.per_wave;
+    const int ngroups = a.segs.total / 16;
+    if (g0 >= ngroups) return;
+    const int g1 = min(g0 + a.per_wave, ngroups);
+    f4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = (f4){0, 0, 0, 0};
+    float dbs = 0.0f;
+    const int cA = lane & 15;          // A row: input channel
+    const int k0 = 4 * (lane >> 4);    // A/B k: pixel offset within the group
+    for (int g = g0; g < g1; ++g) {
+        const int p0 = g * 16;
+        const int sgi = find_seg(a.segs, p0);
+        const int base = a.segs.base[sgi], rows = a.segs.rows[sgi], cols = a.segs.cols[sgi];
+        const int npx = rows * cols;
+        // B: g[p][n] for the lane's 4 pixels, n = lane%16
+        s4 bv;
+        int py[4], px[4];
+        bool pv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = p0 - base + k0 + r;
+            pv[r] = i < npx;
+            py[r] = pv[r] ? i / cols : 0;
+            px[r] = pv[r] ? i - py[r] * cols : 0;
+            uint16_t gv = 0;
+            if (pv[r]) {
+                const size_t off = ((size_t)base + i) * 16 + cA;
+                gv = a.dout[off];
+                if (a.act && bf2f(a.act[off]) <= 0.0f) gv = 0;
+            }
+            bv[r] = (short)gv;
+            dbs += bf2f(gv);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            s4 av;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int yy = py[r] + dy, xx = px[r] + dx;
+                uint16_t v = 0;
+                if (pv[r] && yy >= 0 && yy < rows && xx >= 0 && xx < cols)
+                    v = a.in[((size_t)base + (size_t)yy * cols + xx) * 16 + cA];
+                av[r] = (short)v;
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    // D[i = c][j = n]: lane holds c = 4(lane/16) + r, n = lane%16
+    const int n = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 4 * (lane >> 4) + r;
+            atomicAdd(&a.dw[(t * 16 + c) * 16 + n], acc[t][r]);
+        }
+    // bias: lanes sharing n = lane%16 hold disjoint pixel sets; the B values of channel n are
+    // those with cA == n, i.e. lanes whose lane%16 == n
+    atomicAdd(&a.db[lane & 15], dbs);
+}
+
+// loss: Charbonnier endpoint error between the network's output (FP32 planes, 3 channels) and
+// the target; writes d loss / d output as BF16 NHWC (16 channels, 3 used) and adds the loss.
+__global__ void __launch_bounds__(256) k_loss(LossArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.segs.total) return;
+    const int sgi = find_seg(a.segs, p);
+    const int i = p - a.segs.base[sgi];
+    const bool valid = i < a.segs.rows[sgi] * a.segs.cols[sgi];
+    float d[3] = {0, 0, 0};
+    float n = 1.0f;
+    if (valid) {
+        float s2 = a.eps * a.eps;
+        for (int c = 0; c < 3; ++c) {
+            d[c] = a.out[(size_t)c * a.segs.total + p] - a.target[(size_t)c * a.segs.total + p];
+            s2 = fmaf(d[c], d[c], s2);
+        }
+        n = sqrtf(s2);
+        atomicAdd(a.loss, n * a.inv_count);
+    }
+    for (int c = 0; c < 16; ++c)
+        a.dout[(size_t)p * 16 + c] = (valid && c < 3) ? f2bf(d[c] / n * a.inv_count) : (uint16_t)0;
+}
+
+// FP32 planar inputs (C planes of `total` pixels) -> BF16 NHWC 16 channels
+__global__ void __launch_bounds__(256) k_pack_inputs(const float* in, int C, int total,
+                                                     uint16_t* out) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= total) return;
+    for (int c = 0; c < 16; ++c)
+        out[(size_t)p * 16 + c] = c < C ? f2bf(in[(size_t)c * total + p]) : (uint16_t)0;
+}
+
+// Adam on the FP32 master parameters, then the BF16 weights of the forward kernel
+// ([tap][out 16][in 16]) and of the input-gradient kernel (taps mirrored, in/out swapped).
+__global__ void __launch_bounds__(256) k_adam(AdamArgs a) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q < a.nparams && a.lr > 0.0f) {
+        const float g = a.grad[q];
+        const float m = a.b1 * a.m[q] + (1.0f - a.b1) * g;
+        const float v = a.b2 * a.v[q] + (1.0f - a.b2) * g * g;
+        a.m[q] = m;
+        a.v[q] = v;
+        a.params[q] -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pack_weights(PackArgs a) {
+    const int q = blockIdx.x * 256 + threadIdx.x;     // one entry of the packed 4 x 9 x 16 x 16
+    if (q >= 4 * 9 * 256) return;
+    const int l = q / (9 * 256);
+    const int rem = q - l * 9 * 256;
+    const int t = rem / 256;
+    const int n = (rem / 16) % 16;   // output channel of the forward kernel
+    const int c = rem % 16;          // input channel
+    const int cin = a.cin[l], cout = a.cout[l];
+    const float* W = a.params + a.woff[l];             // (3, 3, cin, cout) row-major
+    const float vf = (c < cin && n < cout) ? W[(t * cin + c) * cout + n] : 0.0f;
+    a.wf[q] = f2bf(vf);
+    // input-gradient kernel of layer l: out channel = forward input c', in channel = forward
+    // output n', tap mirrored: weight (8 - t, c' = n, n' = c)
+    const float vb = (n < cin && c < cout) ? W[((8 - t) * cin + n) * cout + c] : 0.0f;
+    a.wb[q] = f2bf(vb);
+    if (t == 0 && c == 0) a.bias[l * 16 + n] = n < cout ? a.params[a.boff[l] + n] : 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_gather_grads(GradArgs a) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= kCnnParams) return;
+    int l = 0;
+    while (l + 1 < kCnnLayers && a.woff[l + 1] <= q) ++l;
+    const int cin = a.cin[l], cout = a.cout[l];
+    if (q < a.boff[l]) {
+        const int idx = q - a.woff[l];
+        const int t = idx / (cin * cout);
+        const int c = (idx / cout) % cin;
+        const int n = idx % cout;
+        a.grad[q] = a.dw[((size_t)(l * 9 + t) * 16 + c) * 16 + n];
+    } else {
+        a.grad[q] = a.db[l * 16 + (q - a.boff[l])];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_planes_in(CnnSegs sg, const float* src, int C, float* dst) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= sg.total) return;
+    const int k = find_seg(sg, p);
+    const int i = p - sg.base[k];
+    const int npx = sg.rows[k] * sg.cols[k];
+    for (int c = 0; c < C; ++c)
+        dst[(size_t)c * sg.total + p] = i < npx ? src[(size_t)sg.off[k] * C + (size_t)c * npx + i] : 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_planes_out(CnnSegs sg, const float* src, int C, float* dst) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= sg.total) return;
+    const int k = find_seg(sg, p);
+    const int i = p - sg.base[k];
+    const int npx = sg.rows[k] * sg.cols[k];
+    if (i >= npx) return;
+    for (int c = 0; c < C; ++c)
+        dst[(size_t)sg.off[k] * C + (size_t)c * npx + i] = src[(size_t)c * sg.total + p];
+}
+
+}  // namespace
+
+hipError_t launch_gather_grads(const GradArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_grads, dim3((kCnnParams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_in(const CnnSegs& sg, const float* src, int C, float* dst, hipStream_t s) {
+    const int blocks = (sg.total + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_planes_in, dim3(blocks), dim3(256), 0, s, sg, src, C, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes_out(const CnnSegs& sg, const float* src, int C, float* dst, hipStream_t s) {
+    const int blocks = (sg.total + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_planes_out, dim3(blocks), dim3(256), 0, s, sg, src, C, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv(const ConvArgs& a, bool out_f32, hipStream_t s) {
+    const int groups = (a.segs.total + 15) / 16;
+    const int blocks = (groups + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    if (out_f32)
+        hipLaunchKernelGGL(k_conv<true>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_conv<false>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_dw(const DwArgs& a, hipStream_t s) {
+    const int groups = a.segs.total / 16;
+    const int waves = (groups + a.per_wave - 1) / a.per_wave;
+    const int blocks = (waves + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_conv_dw, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const LossArgs& a, hipStream_t s) {
+    const int blocks = (a.segs.total + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_inputs(const float* in, int C, int total, uint16_t* out, hipStream_t s) {
+    const int blocks = (total + 255) / 256;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_inputs, dim3(blocks), dim3(256), 0, s, in, C, total, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((a.nparams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const PackArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_weights, dim3((4 * 9 * 256 + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sflow

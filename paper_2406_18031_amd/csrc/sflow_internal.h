@@ -18,7 +18,17 @@ constexpr size_t kLdsXB = 2 * (kBlock / 64) * 2 * 8 * 64 * sizeof(float);
 constexpr size_t kLdsPlanes = 5 * kRegion * 64 * sizeof(float);
 constexpr size_t kLdsBytes = kLdsXB > kLdsPlanes ? kLdsXB : kLdsPlanes;
 
-// Per-level parameters, uploaded once per camera to device memory.
+constexpr int kMaxStreams = 64;      // camera streams per context
+// Planes of the learned-update buffers of a finest level: network inputs (6), prior x0 (3),
+// least-squares solution (3), cost terms a_Y (3), a_rho (3), G1, G2 (2) and the network's
+// output (3), each `ltotal` floats.
+constexpr int kLearnIn = 0, kLearnX0 = 6, kLearnXP = 9, kLearnFB = 12, kLearnOut = 20;
+constexpr int kLearnPlanes = 23;
+constexpr int kElemBlock = 256;      // threads (pixels) per block of the per-pixel kernels
+
+// Parameters of one pyramid level of one camera stream ("entry"), uploaded to device memory
+// whenever the camera or the tiling changes.  Entries are ordered stream by stream, finest
+// level first.
 struct LevelDev {
     int rows, cols, pitch;           // level size; row pitch (elements) of state/pyramid planes
     float ifx, ify, cxn, cyn;        // x = j*ifx - cxn, y = i*ify - cyn (pinhole ray)
@@ -27,35 +37,71 @@ struct LevelDev {
     float g1, g2, g3, g4, g5;        // gamma_1..gamma_5
     float qscale;                    // half storage: stored flow = flow (rad/frame) * qscale
     int tw, th, tiles_x, tiles_y, block0, halo;
+    int stream, level;               // owning stream; level (0 = finest)
+    int child, parent;               // entries of the next finer / coarser level (-1: none)
+    uint32_t flags;                  // SF_READ_* bits of the stream
+    int learned;                     // 1: the update of this level is the learned one
+    int lbase;                       // first pixel of this level in the learned buffers
+    int ltotal;                      // pixels (padded) of the learned buffers, all streams
+    float* lbuf;                     // learned buffers: kLearnPlanes planes of ltotal floats
     void* w[2][3];                   // state, indexed by parity
     void* dw[2][3];                  // lower levels only
     void* rho[2];
     void* Y[2];
-    void* Ym;                        // pyramid image of this frame (levels >= 2)
-    void* Rm;                        // pyramid inverse depth of this frame (levels >= 2)
+    void* Ym;                        // pyramid image of this frame (levels >= 1)
+    void* Rm;                        // pyramid inverse depth of this frame (levels >= 1)
+};
+
+// Per-frame arguments: the finest-level measurements of every stream (caller's device
+// pointers, pitch = cols) and the dt_new / dt_old rescale of w and dw.
+struct FrameInputs {
+    const void* Y[kMaxStreams];
+    const void* R[kMaxStreams];
+    float scale[kMaxStreams];
 };
 
 struct StepArgs {
     const LevelDev* lv;
-    int nlev;
-    const void* Y1;                  // finest-level measurements of this frame (pitch = cols)
-    const void* R1;
+    int nent;                        // entries; entry e owns blocks [lv[e].block0, lv[e+1].block0)
     int parity;                      // state[parity] is frame k, state[1 - parity] receives k+1
-    float scale;                     // dt_new / dt_old rescale of w and dw (1 when unchanged)
-    uint32_t flags;                  // SF_READ_* bits
+    FrameInputs in;
 };
 
-// kernel launchers (sflow_kernels.hip)
-hipError_t launch_pyramid(int storage, const LevelDev* lv_host, const LevelDev* lv_dev, int h,
-                          const void* Ysrc, const void* Rsrc, int src_pitch, hipStream_t s);
-hipError_t launch_init(int storage, const LevelDev* lv_host, const LevelDev* lv_dev, int h,
-                       const void* Ym, const void* Rm, int meas_pitch, hipStream_t s);
+// A launch of a per-pixel kernel over a list of entries: entry ent[k] owns blocks
+// [blk[k], blk[k+1]) of kElemBlock pixels each.
+struct ElemArgs {
+    const LevelDev* lv;
+    int n;
+    int ent[kMaxStreams];
+    int blk[kMaxStreams + 1];
+    int parity;                      // state parity read/written by the kernel
+    int kind;                        // output kind (k_output)
+    float inv_dt;                    // output scale to rad/s (k_output)
+    float* out;                      // output planes (k_output)
+    FrameInputs in;
+};
+
+// kernel launchers (sflow_kernels.hip); `storage` is SF_FP32 or SF_FP16
+hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s);
+hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds_bytes,
                        hipStream_t s);
-hipError_t launch_reconstruct(int storage, const LevelDev* lv_host, const LevelDev* lv_dev,
-                              int h, int parity_out, hipStream_t s);
-hipError_t launch_output(int storage, const LevelDev* lv_host, const LevelDev* lv_dev,
-                         int parity, int kind, float inv_dt, float* out, hipStream_t s);
+hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s);
+hipError_t launch_output(int storage, const ElemArgs& a, hipStream_t s);
+hipError_t launch_learned_extract(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t prepare_kernels(size_t max_lds_bytes);
+
+// learned update: choose between the network's and the least-squares solution per pixel,
+// smooth, store the finest level's new flow state (one launch for all streams)
+struct CombineArgs {
+    const LevelDev* lv;
+    int n;
+    int ent[kMaxStreams];
+    int blk[kMaxStreams + 1];        // blocks of 32 x 32 output pixels per entry
+    int parity;                      // state parity written
+    float threshold;                 // fallback when the cost increase exceeds it
+    unsigned long long* fallbacks;   // accumulated count of pixels that fell back
+};
+hipError_t launch_combine(int storage, const CombineArgs& a, hipStream_t s);
 
 }  // namespace sflow

@@ -71,6 +71,19 @@ __device__ __forceinline__ Geo pixel_geo(const LevelDev& L, int i, int j) {
     return g;
 }
 
+// dmu = sqrt(1 - eta_x^2) / (fx |r_n|), computed as in the update stage of k_step
+__device__ __forceinline__ float pixel_dmu(const LevelDev& L, int i, int j) {
+    const float x = fmaf((float)j, L.ifx, -L.cxn);
+    const float xn = x + (j < L.cols - 1 ? L.ifx : -L.ifx);
+    const float y = fmaf((float)i, L.ify, -L.cyn);
+    const float yy1 = fmaf(y, y, 1.0f);
+    const float r2 = fmaf(x, x, yy1);
+    const float rinv = rsqrtf(r2);
+    const float fxrn = L.fx * sqrtf(fmaf(xn, xn, yy1));
+    const float q = sqrtf(fmaf(y, y, 1.0f)) * rinv;
+    return q / fxrn;
+}
+
 __device__ __forceinline__ float flow_u(const Geo& g, float wx, float wy, float wz) {
     return g.fxrn * (wx - g.x * fmaf(g.y, wy, wz) * g.inv1py2);
 }
@@ -232,7 +245,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     // ---- load the frame-k state of the region into registers ------------------------------
     float F[RPW][NF];
     {
-        const float fs = flow_in_scale<T>(L) * a.scale;
+        const float fs = flow_in_scale<T>(L) * a.in.scale[L.stream];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int i = wi0 + r;
@@ -257,10 +270,10 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const int N = L.N;
     const float dt = 1.0f / (float)N;
     const float fN = (float)N;
-    const float sig = (a.flags & SF_READ_SOURCE_LITERAL) ? 1.0f : 0.5f;
+    const float sig = (L.flags & SF_READ_SOURCE_LITERAL) ? 1.0f : 0.5f;
     const float dtsig = dt * sig;
-    const bool dom_lit = (a.flags & SF_READ_DOMINANT_LITERAL) != 0;
-    const bool cfl = (a.flags & SF_READ_NO_CFL_CLAMP) == 0;
+    const bool dom_lit = (L.flags & SF_READ_DOMINANT_LITERAL) != 0;
+    const bool cfl = (L.flags & SF_READ_NO_CFL_CLAMP) == 0;
     int ci0 = vi0, ci1 = vi1, cj0 = vj0, cj1 = vj1;
     float* XB = lds;   // [2][NW][2][NF][64] boundary rows of every wave, double-buffered
 
@@ -345,8 +358,8 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     float* PHG = lds;                    // [64 rows][64 lanes]
     float* PHD = lds + kRegion * 64;
     float* PT = lds + 2 * kRegion * 64;  // [3][64][64] smoothing
-    const T* Ymeas = (const T*)(h == 0 ? a.Y1 : L.Ym);
-    const T* Rmeas = (const T*)(h == 0 ? a.R1 : L.Rm);
+    const T* Ymeas = (const T*)(h == 0 ? a.in.Y[L.stream] : L.Ym);
+    const T* Rmeas = (const T*)(h == 0 ? a.in.R[L.stream] : L.Rm);
     const int mp = h == 0 ? C : L.pitch;
     const bool mcol = lane < RW && j >= mj0 && j < mj1;
 
@@ -448,6 +461,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
             const float al = -G1 * fmaf(res1, sg3, G2 * (res1 * bb - ab * res2)) / det;
             const float be = -G2 * fmaf(res2, sg3, G1 * (res2 * aa2 - ab * res1)) / det;
             const float rpred = F[r][KR];
+            const float px0 = F[r][KX], py0 = F[r][KX + 1], pz0 = F[r][KX + 2];
             F[r][KX] = fmaf(al, aYx, fmaf(be, aRx, x0)) * dmu;
             F[r][KX + 1] = fmaf(al, aYy, fmaf(be, aRy, y0)) * dmu;
             F[r][KX + 2] = fmaf(al, aYz, fmaf(be, aRz, z0)) * dmu;
@@ -455,9 +469,38 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 const float rn = rv ? (L.g4 * rc + L.g5 * rpred) / (L.g4 + L.g5) : rpred;
                 stv(Rout, gs, rn);
                 stv(Yout, gs, Yh);
+                if (L.learned) {
+                    // inputs of the learned update, its prior, the least-squares solution and
+                    // the cost terms that judge the network's answer
+                    float* lb = L.lbuf + L.lbase + (size_t)(i * C + j);
+                    const size_t P = (size_t)L.ltotal;
+                    lb[(kLearnIn + 0) * P] = Yprior - 0.5f;
+                    lb[(kLearnIn + 1) * P] = Yh - 0.5f;
+                    lb[(kLearnIn + 2) * P] = rv ? 4.0f * rc : 0.0f;
+                    lb[(kLearnIn + 3) * P] = x0 * 0.25f;
+                    lb[(kLearnIn + 4) * P] = y0 * 0.25f;
+                    lb[(kLearnIn + 5) * P] = z0 * 0.25f;
+                    lb[(kLearnX0 + 0) * P] = px0;
+                    lb[(kLearnX0 + 1) * P] = py0;
+                    lb[(kLearnX0 + 2) * P] = pz0;
+                    lb[(kLearnXP + 0) * P] = F[r][KX];
+                    lb[(kLearnXP + 1) * P] = F[r][KX + 1];
+                    lb[(kLearnXP + 2) * P] = F[r][KX + 2];
+                    lb[(kLearnFB + 0) * P] = aYx;
+                    lb[(kLearnFB + 1) * P] = aYy;
+                    lb[(kLearnFB + 2) * P] = aYz;
+                    lb[(kLearnFB + 3) * P] = aRx;
+                    lb[(kLearnFB + 4) * P] = aRy;
+                    lb[(kLearnFB + 5) * P] = aRz;
+                    lb[(kLearnFB + 6) * P] = G1;
+                    lb[(kLearnFB + 7) * P] = G2;
+                }
             }
         }
     }
+
+    // the learned update chooses, smooths and stores this level's flow in its own kernel
+    if (L.learned) return;
 
     // ---- smoothing: N_s passes of the 5x5 average ---------------------------------------------
     constexpr int KX = TOP ? 0 : 3;
@@ -519,35 +562,55 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     extern __shared__ float lds[];
     const int b = blockIdx.x;
-    int h = 0;
-    for (int k = 1; k < a.nlev; ++k)
-        if (b >= a.lv[k].block0) h = k;
-    const LevelDev& L = a.lv[h];
+    // the entry owning this block: the last one whose first block is <= b
+    int lo = 0, hi = a.nent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.lv[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const LevelDev& L = a.lv[lo];
     if (L.top)
-        level_tile<T, true>(a, L, h, b - L.block0, lds);
+        level_tile<T, true>(a, L, L.level, b - L.block0, lds);
     else
-        level_tile<T, false>(a, L, h, b - L.block0, lds);
+        level_tile<T, false>(a, L, L.level, b - L.block0, lds);
+}
+
+// The entry and pixel of a per-pixel launch; false past the entry's last pixel.
+__device__ __forceinline__ bool elem_pixel(const ElemArgs& a, int& e, int& i, int& j) {
+    const int b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
+    e = a.ent[k];
+    const LevelDev& L = a.lv[e];
+    const int p = (b - a.blk[k]) * kElemBlock + threadIdx.x;
+    if (p >= L.rows * L.cols) return false;
+    i = p / L.cols;
+    j = p - i * L.cols;
+    return true;
 }
 
 // ------------------------------------------------------------------------------------------
 // pyramid: level h+1 = 5x5 Gaussian blur of level h sampled at (2i, 2j); inverse depth
-// blurred over valid samples only (missing if none)
+// blurred over valid samples only (missing if none).  The entry is the destination level.
 // ------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_pyramid(const T* Ys, const T* Rs, int sp, int Rsrc,
-                                                 int Csrc, T* Yd, T* Rd, int dp, int Rdst,
-                                                 int Cdst) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= Cdst || i >= Rdst) return;
+__global__ void __launch_bounds__(kElemBlock) k_pyramid(ElemArgs a) {
+    int e, i, j;
+    if (!elem_pixel(a, e, i, j)) return;
+    const LevelDev& D = a.lv[e];
+    const LevelDev& S = a.lv[D.child];
+    const bool fin = S.level == 0;
+    const T* Ys = (const T*)(fin ? a.in.Y[D.stream] : S.Ym);
+    const T* Rs = (const T*)(fin ? a.in.R[D.stream] : S.Rm);
+    const int sp = fin ? S.cols : S.pitch;
     float acc = 0.0f, num = 0.0f, den = 0.0f;
 #pragma unroll
     for (int aa = -2; aa <= 2; ++aa) {
-        const size_t row = (size_t)clampi(2 * i + aa, 0, Rsrc - 1) * sp;
+        const size_t row = (size_t)clampi(2 * i + aa, 0, S.rows - 1) * sp;
 #pragma unroll
         for (int bb = -2; bb <= 2; ++bb) {
             const float w = gtap(aa) * gtap(bb);
-            const size_t idx = row + clampi(2 * j + bb, 0, Csrc - 1);
+            const size_t idx = row + clampi(2 * j + bb, 0, S.cols - 1);
             acc = fmaf(w, ldv(Ys, idx), acc);
             const float r = ldv(Rs, idx);
             if (!isnan(r)) {
@@ -556,18 +619,20 @@ __global__ void __launch_bounds__(256) k_pyramid(const T* Ys, const T* Rs, int s
             }
         }
     }
-    stv(Yd, (size_t)i * dp + j, acc);
-    stv(Rd, (size_t)i * dp + j, den > 0.0f ? num / den : __int_as_float(0x7fc00000));
+    stv((T*)D.Ym, (size_t)i * D.pitch + j, acc);
+    stv((T*)D.Rm, (size_t)i * D.pitch + j, den > 0.0f ? num / den : __int_as_float(0x7fc00000));
 }
 
 // first frame: Yhat = G * Y, rho = measured (0 where missing), w = dw = 0, into state[0]
 template <typename T>
-__global__ void __launch_bounds__(256) k_init(const LevelDev* lvp, int h, const T* Ym,
-                                              const T* Rm, int mp) {
-    const LevelDev& L = lvp[h];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= L.cols || i >= L.rows) return;
+__global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
+    int e, i, j;
+    if (!elem_pixel(a, e, i, j)) return;
+    const LevelDev& L = a.lv[e];
+    const bool fin = L.level == 0;
+    const T* Ym = (const T*)(fin ? a.in.Y[L.stream] : L.Ym);
+    const T* Rm = (const T*)(fin ? a.in.R[L.stream] : L.Rm);
+    const int mp = fin ? L.cols : L.pitch;
     // same separable order of operations as the image model of k_step, so that a static
     // scene reproduces Yhat bit for bit
     float acc = 0.0f;
@@ -590,14 +655,14 @@ __global__ void __launch_bounds__(256) k_init(const LevelDev* lvp, int h, const 
     }
 }
 
-// reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[q]
+// reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[parity]
 template <typename T>
-__global__ void __launch_bounds__(256) k_reconstruct(const LevelDev* lvp, int h, int q) {
-    const LevelDev& L = lvp[h];
-    const LevelDev& U = lvp[h + 1];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= L.cols || i >= L.rows) return;
+__global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
+    int e, i, j;
+    if (!elem_pixel(a, e, i, j)) return;
+    const LevelDev& L = a.lv[e];
+    const LevelDev& U = a.lv[L.parent];
+    const int q = a.parity;
     const int i0 = i >> 1, j0 = j >> 1;
     const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
     const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
@@ -616,18 +681,18 @@ __global__ void __launch_bounds__(256) k_reconstruct(const LevelDev* lvp, int h,
     }
 }
 
-// finest-level outputs
+// finest-level outputs of one stream (a single entry)
 template <typename T>
-__global__ void __launch_bounds__(256) k_output(const LevelDev* lvp, int q, int kind,
-                                                float inv_dt, float* out) {
-    const LevelDev& L = lvp[0];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    if (j >= L.cols || i >= L.rows) return;
+__global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
+    int e, i, j;
+    if (!elem_pixel(a, e, i, j)) return;
+    const LevelDev& L = a.lv[e];
+    const int q = a.parity;
+    float* out = a.out;
     const size_t go = (size_t)i * L.pitch + j;
     const size_t plane = (size_t)L.rows * L.cols;
     const size_t o = (size_t)i * L.cols + j;
-    if (kind == SF_FLOW_RHO) {
+    if (a.kind == SF_FLOW_RHO) {
         out[o] = ldv((const T*)L.rho[q], go);
         return;
     }
@@ -635,21 +700,161 @@ __global__ void __launch_bounds__(256) k_output(const LevelDev* lvp, int q, int 
     const float wx = ldv((const T*)L.w[q][0], go) * fs;
     const float wy = ldv((const T*)L.w[q][1], go) * fs;
     const float wz = ldv((const T*)L.w[q][2], go) * fs;
-    if (kind == SF_FLOW_W_RAD_S || kind == SF_FLOW_W_FRAME) {
-        const float m = kind == SF_FLOW_W_RAD_S ? inv_dt : 1.0f;
+    if (a.kind == SF_FLOW_W_RAD_S || a.kind == SF_FLOW_W_FRAME) {
+        const float m = a.kind == SF_FLOW_W_RAD_S ? a.inv_dt : 1.0f;
         out[o] = wx * m;
         out[o + plane] = wy * m;
         out[o + 2 * plane] = wz * m;
         return;
     }
     const Geo g = pixel_geo(L, i, j);
-    if (kind == SF_FLOW_TANGENT_PX) {
+    if (a.kind == SF_FLOW_TANGENT_PX) {
         out[o] = flow_u(g, wx, wy, wz);
         out[o + plane] = flow_v(g, wx, wy, wz);
     } else {   // normal: <eta, w> / dmu with dmu = sqrt(1 - eta_x^2) / (fx |r_n|)
         const float q2 = sqrtf(fmaf(g.y, g.y, 1.0f)) * g.rinv;
         out[o] = normal_s(g, wx, wy, wz) * g.fxrn / q2;
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// learned update: per pixel, the network's flow x0 + dmu * out unless its increase of the
+// least-squares cost over the least-squares solution exceeds the threshold; then the level's
+// N_s passes of 5x5 averaging (same order of operations as in k_step) and the state store.
+// One block = 32 x 32 output pixels plus a halo of 2 N_s (N_s <= 4).
+// ------------------------------------------------------------------------------------------
+constexpr int kCombTile = 32;
+constexpr int kCombMaxRegion = kCombTile + 2 * 2 * 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
+    __shared__ float X[3][kCombMaxRegion * kCombMaxRegion];
+    __shared__ float TM[3][kCombMaxRegion * kCombMaxRegion];
+    __shared__ unsigned int nfb;
+    const int b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
+    const LevelDev& L = a.lv[a.ent[k]];
+    const int R = L.rows, C = L.cols;
+    const int t = b - a.blk[k];
+    const int tilesx = (C + kCombTile - 1) / kCombTile;
+    const int ty = t / tilesx, tx = t - ty * tilesx;
+    const int ti0 = ty * kCombTile, tj0 = tx * kCombTile;
+    const int ti1 = min(ti0 + kCombTile, R), tj1 = min(tj0 + kCombTile, C);
+    const int Ns = L.Ns;
+    const int hal = 2 * Ns;
+    const int gi0 = ti0 - hal, gj0 = tj0 - hal;
+    const int RW = kCombTile + 2 * hal;
+    const int vi0 = max(gi0, 0), vi1 = min(ti1 + hal, R);
+    const int vj0 = max(gj0, 0), vj1 = min(tj1 + hal, C);
+    if (threadIdx.x == 0) nfb = 0;
+    __syncthreads();
+    const size_t P = (size_t)L.ltotal;
+    const float* lb = L.lbuf + L.lbase;
+    unsigned int myfb = 0;
+    for (int q = threadIdx.x; q < (vi1 - vi0) * (vj1 - vj0); q += 256) {
+        const int i = vi0 + q / (vj1 - vj0);
+        const int j = vj0 + q % (vj1 - vj0);
+        const size_t p = (size_t)i * C + j;
+        const float dmu = pixel_dmu(L, i, j);
+        float xc[3], xp[3], d[3];
+        for (int c = 0; c < 3; ++c) {
+            xp[c] = lb[(kLearnXP + c) * P + p];
+            xc[c] = fmaf(dmu, lb[(kLearnOut + c) * P + p], lb[(kLearnX0 + c) * P + p]);
+            d[c] = (xc[c] - xp[c]) / dmu;
+        }
+        const float eY = lb[(kLearnFB + 0) * P + p] * d[0] + lb[(kLearnFB + 1) * P + p] * d[1] +
+                         lb[(kLearnFB + 2) * P + p] * d[2];
+        const float eR = lb[(kLearnFB + 3) * P + p] * d[0] + lb[(kLearnFB + 4) * P + p] * d[1] +
+                         lb[(kLearnFB + 5) * P + p] * d[2];
+        const float cost = lb[(kLearnFB + 6) * P + p] * eY * eY +
+                           lb[(kLearnFB + 7) * P + p] * eR * eR +
+                           L.g3 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const bool fb = !(cost <= a.threshold);     // NaN falls back too
+        const int li = (i - gi0) * RW + (j - gj0);
+        for (int c = 0; c < 3; ++c) X[c][li] = fb ? xp[c] : xc[c];
+        if (fb && i >= ti0 && i < ti1 && j >= tj0 && j < tj1) ++myfb;
+    }
+    if (myfb) atomicAdd(&nfb, myfb);
+    __syncthreads();
+    for (int sp = 1; sp <= Ns; ++sp) {
+        const int rad = 2 * (Ns - sp);
+        const int oi0 = max(ti0 - rad, 0), oi1 = min(ti1 + rad, R);
+        const int oj0 = max(tj0 - rad, 0), oj1 = min(tj1 + rad, C);
+        const int ii0 = max(oi0 - 2, 0), ii1 = min(oi1 + 2, R);
+        for (int q = threadIdx.x; q < (ii1 - ii0) * (oj1 - oj0); q += 256) {
+            const int i = ii0 + q / (oj1 - oj0);
+            const int j = oj0 + q % (oj1 - oj0);
+            const int row = (i - gi0) * RW - gj0;
+            for (int c = 0; c < 3; ++c) {
+                const float m2 = X[c][row + clampi(j - 2, 0, C - 1)];
+                const float m1 = X[c][row + clampi(j - 1, 0, C - 1)];
+                const float v0 = X[c][row + j];
+                const float p1 = X[c][row + clampi(j + 1, 0, C - 1)];
+                const float p2 = X[c][row + clampi(j + 2, 0, C - 1)];
+                TM[c][(i - gi0) * RW + (j - gj0)] = (((m2 + m1) + v0) + p1) + p2;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < (oi1 - oi0) * (oj1 - oj0); q += 256) {
+            const int i = oi0 + q / (oj1 - oj0);
+            const int j = oj0 + q % (oj1 - oj0);
+            for (int c = 0; c < 3; ++c) {
+                float s = 0.0f;
+                for (int aa = -2; aa <= 2; ++aa)
+                    s += TM[c][(clampi(i + aa, 0, R - 1) - gi0) * RW + (j - gj0)];
+                X[c][(i - gi0) * RW + (j - gj0)] = s * 0.04f;
+            }
+        }
+        __syncthreads();
+    }
+    const float os = flow_out_scale<T>(L);
+    const int q2 = a.parity;
+    for (int q = threadIdx.x; q < (ti1 - ti0) * (tj1 - tj0); q += 256) {
+        const int i = ti0 + q / (tj1 - tj0);
+        const int j = tj0 + q % (tj1 - tj0);
+        const size_t go = (size_t)i * L.pitch + j;
+        const int li = (i - gi0) * RW + (j - gj0);
+        for (int c = 0; c < 3; ++c) {
+            T* dst = (T*)(L.top ? L.w[q2][c] : L.dw[q2][c]);
+            stv(dst, go, X[c][li] * os);
+        }
+    }
+    if (threadIdx.x == 0 && nfb) atomicAdd(a.fallbacks, (unsigned long long)nfb);
+}
+
+// Learned-update training data of one stream's finest level, after its frame: 16 float32
+// planes [network inputs (6), prior (3), least-squares solution (3), parent flow (3), dmu],
+// flows in the level's field units (rad/frame; the increment at a level with a parent).
+template <typename T>
+__global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
+    int e, i, j;
+    if (!elem_pixel(a, e, i, j)) return;
+    const LevelDev& L = a.lv[e];
+    const size_t npx = (size_t)L.rows * L.cols;
+    const size_t o = (size_t)i * L.cols + j;
+    const size_t P = (size_t)L.ltotal;
+    const float* lb = L.lbuf + L.lbase + o;
+    for (int k = 0; k < 12; ++k) a.out[k * npx + o] = lb[k * P];
+    float base[3] = {0.0f, 0.0f, 0.0f};
+    if (!L.top) {
+        const LevelDev& U = a.lv[L.parent];
+        const int q = a.parity;
+        const int i0 = i >> 1, j0 = j >> 1;
+        const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
+        const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
+        const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
+        const float w10 = fi * (1.0f - fj), w11 = fi * fj;
+        const float uin = flow_in_scale<T>(U);
+        for (int k = 0; k < 3; ++k) {
+            const T* W = (const T*)U.w[q][k];
+            base[k] = (w00 * ldv(W, (size_t)i0 * U.pitch + j0) + w01 * ldv(W, (size_t)i0 * U.pitch + j1) +
+                       w10 * ldv(W, (size_t)i1 * U.pitch + j0) + w11 * ldv(W, (size_t)i1 * U.pitch + j1)) *
+                      uin;
+        }
+    }
+    for (int k = 0; k < 3; ++k) a.out[(12 + k) * npx + o] = base[k];
+    a.out[15 * npx + o] = pixel_dmu(L, i, j);
 }
 
 }  // namespace
@@ -666,31 +871,23 @@ hipError_t prepare_kernels(size_t max_lds_bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
 }
 
-hipError_t launch_pyramid(int storage, const LevelDev* lv, const LevelDev*, int h,
-                          const void* Ysrc, const void* Rsrc, int src_pitch, hipStream_t s) {
-    const LevelDev& S = lv[h];
-    const LevelDev& D = lv[h + 1];
-    dim3 grid((D.cols + 255) / 256, D.rows);
+static int elem_blocks(const ElemArgs& a) { return a.blk[a.n]; }
+
+hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_pyramid<__half>, grid, dim3(256), 0, s, (const __half*)Ysrc,
-                           (const __half*)Rsrc, src_pitch, S.rows, S.cols, (__half*)D.Ym,
-                           (__half*)D.Rm, D.pitch, D.rows, D.cols);
+        hipLaunchKernelGGL(k_pyramid<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_pyramid<float>, grid, dim3(256), 0, s, (const float*)Ysrc,
-                           (const float*)Rsrc, src_pitch, S.rows, S.cols, (float*)D.Ym,
-                           (float*)D.Rm, D.pitch, D.rows, D.cols);
+        hipLaunchKernelGGL(k_pyramid<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, const LevelDev* lv, const LevelDev* lv_dev, int h,
-                       const void* Ym, const void* Rm, int mp, hipStream_t s) {
-    dim3 grid((lv[h].cols + 255) / 256, lv[h].rows);
+hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_init<__half>, grid, dim3(256), 0, s, lv_dev, h, (const __half*)Ym,
-                           (const __half*)Rm, mp);
+        hipLaunchKernelGGL(k_init<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, s, lv_dev, h, (const float*)Ym,
-                           (const float*)Rm, mp);
+        hipLaunchKernelGGL(k_init<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -702,24 +899,40 @@ hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds, 
     return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(int storage, const LevelDev* lv, const LevelDev* lv_dev, int h,
-                              int q, hipStream_t s) {
-    dim3 grid((lv[h].cols + 255) / 256, lv[h].rows);
+hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_reconstruct<__half>, grid, dim3(256), 0, s, lv_dev, h, q);
+        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_reconstruct<float>, grid, dim3(256), 0, s, lv_dev, h, q);
+        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_output(int storage, const LevelDev* lv, const LevelDev* lv_dev, int q,
-                         int kind, float inv_dt, float* out, hipStream_t s) {
-    dim3 grid((lv[0].cols + 255) / 256, lv[0].rows);
+hipError_t launch_output(int storage, const ElemArgs& a, hipStream_t s) {
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_output<__half>, grid, dim3(256), 0, s, lv_dev, q, kind, inv_dt, out);
+        hipLaunchKernelGGL(k_output<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_output<float>, grid, dim3(256), 0, s, lv_dev, q, kind, inv_dt, out);
+        hipLaunchKernelGGL(k_output<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     return hipGetLastError();
 }
 
+}  // namespace sflow
+
+namespace sflow {
+hipError_t launch_learned_extract(int storage, const ElemArgs& a, hipStream_t s) {
+    if (storage == SF_FP16)
+        hipLaunchKernelGGL(k_learned_extract<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_learned_extract<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int storage, const CombineArgs& a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (storage == SF_FP16)
+        hipLaunchKernelGGL(k_combine<__half>, dim3(a.blk[a.n]), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_combine<float>, dim3(a.blk[a.n]), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 }  // namespace sflow

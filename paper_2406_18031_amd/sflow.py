@@ -33,6 +33,8 @@ SF_MAX_LEVELS = 8
 FLOW_COMPONENTS = {SF_FLOW_W_RAD_S: 3, SF_FLOW_TANGENT_PX: 2, SF_FLOW_NORMAL_PX: 1,
                    SF_FLOW_RHO: 1, SF_FLOW_W_FRAME: 3}
 DEFAULT_ALPHA = (300.0, 1000.0, 1.0, 1.0, 1.0)
+SF_LEARNED_PARAMS = 5955
+SF_UPDATE_INPUT_PLANES = 16
 
 
 class sf_config(ctypes.Structure):
@@ -73,6 +75,28 @@ def _load():
         "sf_set_timing": (st, [vp, ctypes.c_int32]),
         "sf_kernel_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+        "sf_create_batch": (st, [ctypes.POINTER(sf_config), ctypes.c_int32, vp,
+                                 ctypes.POINTER(vp)]),
+        "sf_stream_count": (st, [vp, ctypes.POINTER(ctypes.c_int32)]),
+        "sf_set_cameras": (st, [vp, ctypes.POINTER(sf_camera)]),
+        "sf_push_frames": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                ctypes.POINTER(ctypes.c_double)]),
+        "sf_get_flow_stream": (st, [vp, ctypes.c_int32, ctypes.c_int32, vp]),
+        "sf_state_size_stream": (st, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+        "sf_get_state_stream": (st, [vp, ctypes.c_int32, vp, ctypes.c_size_t]),
+        "sf_set_state_stream": (st, [vp, ctypes.c_int32, vp, ctypes.c_size_t]),
+        "sf_set_learned": (st, [vp, vp, ctypes.c_size_t, ctypes.c_float]),
+        "sf_learned_stats": (st, [vp, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+        "sf_get_update_inputs": (st, [vp, ctypes.c_int32, vp]),
+        "sf_net_create": (st, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                               ctypes.c_int32, vp, ctypes.POINTER(vp)]),
+        "sf_net_set_params": (st, [vp, vp, ctypes.c_size_t]),
+        "sf_net_get_params": (st, [vp, vp, ctypes.c_size_t]),
+        "sf_net_forward": (st, [vp, vp, vp]),
+        "sf_net_train_step": (st, [vp, vp, vp, ctypes.c_float, vp, vp]),
+        "sf_net_destroy": (st, [vp]),
+        "sf_net_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -84,7 +108,11 @@ def _load():
 lib = _load()
 EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_state_size",
             "sf_get_state", "sf_set_state", "sf_destroy", "sf_last_error", "sf_set_tile",
-            "sf_set_timing", "sf_kernel_times")
+            "sf_set_timing", "sf_kernel_times", "sf_create_batch", "sf_stream_count",
+            "sf_set_cameras", "sf_push_frames", "sf_get_flow_stream", "sf_state_size_stream",
+            "sf_get_state_stream", "sf_set_state_stream", "sf_set_learned", "sf_learned_stats",
+            "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
+            "sf_net_forward", "sf_net_train_step", "sf_net_destroy", "sf_net_last_error")
 
 
 def _check(status: int, ctx) -> None:
@@ -116,6 +144,13 @@ def make_config(rows: int, cols: int, levels: int, max_flow_px: float,
 
 
 # ---- the C calls, same names ------------------------------------------------------------
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    return ctypes.c_void_p(stream)
+
+
 def sf_create(cfg: sf_config, stream=None) -> int:
     if stream is None:
         import torch
@@ -180,7 +215,122 @@ def sf_kernel_times(ctx: int, reset: bool = False):
     return list(ms), list(n)
 
 
+def sf_create_batch(cfgs: Sequence[sf_config], stream=None) -> int:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    arr = (sf_config * len(cfgs))(*cfgs)
+    out = ctypes.c_void_p()
+    _check(lib.sf_create_batch(arr, len(cfgs), ctypes.c_void_p(stream), ctypes.byref(out)), None)
+    return out.value
+
+
+def sf_stream_count(ctx: int) -> int:
+    n = ctypes.c_int32()
+    _check(lib.sf_stream_count(ctx, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def sf_set_cameras(ctx: int, cams: Sequence[Sequence[float]]) -> None:
+    arr = (sf_camera * len(cams))(*[sf_camera(*c) for c in cams])
+    _check(lib.sf_set_cameras(ctx, arr), ctx)
+
+
+def sf_push_frames(ctx: int, Ys, rhos, dts) -> None:
+    n = len(Ys)
+    y = (ctypes.c_void_p * n)(*[_ptr(t) for t in Ys])
+    r = (ctypes.c_void_p * n)(*[_ptr(t) for t in rhos])
+    d = (ctypes.c_double * n)(*[float(v) for v in dts])
+    _check(lib.sf_push_frames(ctx, y, r, d), ctx)
+
+
+def sf_get_flow_stream(ctx: int, stream: int, kind: int, out) -> None:
+    _check(lib.sf_get_flow_stream(ctx, stream, kind, _ptr(out)), ctx)
+
+
+def sf_state_size_stream(ctx: int, stream: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib.sf_state_size_stream(ctx, stream, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def sf_get_state_stream(ctx: int, stream: int) -> bytes:
+    n = sf_state_size_stream(ctx, stream)
+    buf = ctypes.create_string_buffer(n)
+    _check(lib.sf_get_state_stream(ctx, stream, buf, n), ctx)
+    return buf.raw
+
+
+def sf_set_state_stream(ctx: int, stream: int, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    _check(lib.sf_set_state_stream(ctx, stream, buf, len(blob)), ctx)
+
+
 # ---- state blob layout (header + float32 planes, see include/sflow.h) ---------------------
+def _f32(params) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    if a.size != SF_LEARNED_PARAMS:
+        raise ValueError(f"expected {SF_LEARNED_PARAMS} parameters, got {a.size}")
+    return a
+
+
+def sf_set_learned(ctx: int, params, threshold: float) -> None:
+    a = _f32(params)
+    _check(lib.sf_set_learned(ctx, a.ctypes.data, a.size, threshold), ctx)
+
+
+def sf_learned_stats(ctx: int, reset: bool = False):
+    fb, px = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.sf_learned_stats(ctx, ctypes.byref(fb), ctypes.byref(px), int(reset)), ctx)
+    return fb.value, px.value
+
+
+def sf_get_update_inputs(ctx: int, stream: int, out) -> None:
+    _check(lib.sf_get_update_inputs(ctx, stream, _ptr(out)), ctx)
+
+
+def _net_check(status: int, net) -> None:
+    if status != SF_OK:
+        msg = lib.sf_net_last_error(net)
+        raise SflowError(status, msg.decode() if msg else "")
+
+
+def sf_net_create(sizes: Sequence[Sequence[int]], stream=None) -> int:
+    n = len(sizes)
+    rows = (ctypes.c_int32 * max(n, 1))(*[int(r) for r, _ in sizes])
+    cols = (ctypes.c_int32 * max(n, 1))(*[int(c) for _, c in sizes])
+    out = ctypes.c_void_p()
+    _net_check(lib.sf_net_create(rows, cols, n, _stream(stream), ctypes.byref(out)), None)
+    return out.value
+
+
+def sf_net_set_params(net: int, params) -> None:
+    a = _f32(params)
+    _net_check(lib.sf_net_set_params(net, a.ctypes.data, a.size), net)
+
+
+def sf_net_get_params(net: int) -> np.ndarray:
+    a = np.empty(SF_LEARNED_PARAMS, dtype=np.float32)
+    _net_check(lib.sf_net_get_params(net, a.ctypes.data, a.size), net)
+    return a
+
+
+def sf_net_forward(net: int, inp, out) -> None:
+    _net_check(lib.sf_net_forward(net, _ptr(inp), _ptr(out)), net)
+
+
+def sf_net_train_step(net: int, inp, target, lr: float, want_grad: bool = False):
+    loss = np.zeros(1, dtype=np.float32)
+    grad = np.empty(SF_LEARNED_PARAMS, dtype=np.float32) if want_grad else None
+    _net_check(lib.sf_net_train_step(net, _ptr(inp), _ptr(target), lr, loss.ctypes.data,
+                                     grad.ctypes.data if want_grad else None), net)
+    return float(loss[0]), grad
+
+
+def sf_net_destroy(net: int) -> None:
+    _net_check(lib.sf_net_destroy(net), net)
+
+
 def level_shapes(rows: int, cols: int, levels: int):
     out, r, c = [], rows, cols
     for _ in range(levels):
@@ -233,11 +383,12 @@ class Filter:
     """Convenience wrapper owning one context; inputs are torch CUDA tensors."""
 
     def __init__(self, rows, cols, levels, max_flow_px, smooth_iters, fx, fy, cx, cy,
-                 alpha=DEFAULT_ALPHA, storage=SF_FP32, read_flags=0, stream=None):
+                 alpha=DEFAULT_ALPHA, storage=SF_FP32, read_flags=0, stream=None,
+                 update=SF_UPDATE_PLAIN):
         self.rows, self.cols, self.levels = rows, cols, levels
         self.storage = storage
         self.cfg = make_config(rows, cols, levels, max_flow_px, smooth_iters, alpha, storage,
-                               SF_UPDATE_PLAIN, read_flags)
+                               update, read_flags)
         self.ctx = sf_create(self.cfg, stream)
         sf_set_camera(self.ctx, fx, fy, cx, cy)
 
@@ -252,11 +403,119 @@ class Filter:
         sf_get_flow(self.ctx, kind, out)
         return out
 
+    def update_inputs(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((SF_UPDATE_INPUT_PLANES, self.rows, self.cols), dtype=torch.float32,
+                              device="cuda")
+        sf_get_update_inputs(self.ctx, 0, out)
+        return out
+
     def get_state(self):
         return unpack_state(sf_get_state(self.ctx), self.rows, self.cols, self.levels)
 
     def set_state(self, state, dt_prev, frames=1):
         sf_set_state(self.ctx, pack_state(state, self.rows, self.cols, self.levels, dt_prev, frames))
+
+    def set_learned(self, params, threshold):
+        sf_set_learned(self.ctx, params, threshold)
+
+    def learned_stats(self, reset=False):
+        return sf_learned_stats(self.ctx, reset)
+
+    def close(self):
+        if self.ctx:
+            sf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """Convenience wrapper owning one trainer network over a fixed list of image sizes."""
+
+    def __init__(self, sizes, params, stream=None):
+        self.sizes = [(int(r), int(c)) for r, c in sizes]
+        self.net = sf_net_create(self.sizes, stream)
+        sf_net_set_params(self.net, params)
+
+    def forward(self, inp, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(3 * sum(r * c for r, c in self.sizes), dtype=torch.float32,
+                              device="cuda")
+        sf_net_forward(self.net, inp, out)
+        return out
+
+    def train_step(self, inp, target, lr, want_grad=False):
+        return sf_net_train_step(self.net, inp, target, lr, want_grad)
+
+    def params(self):
+        return sf_net_get_params(self.net)
+
+    def set_params(self, params):
+        sf_net_set_params(self.net, params)
+
+    def close(self):
+        if self.net:
+            sf_net_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Convenience wrapper owning one batch context (several camera streams)."""
+
+    def __init__(self, specs, storage=SF_FP32, stream=None, update=SF_UPDATE_PLAIN):
+        """specs: list of dicts with rows, cols, levels, max_flow_px, smooth, camera (fx, fy,
+        cx, cy) and optionally alpha, read_flags."""
+        self.specs = list(specs)
+        cfgs = [make_config(sp["rows"], sp["cols"], sp["levels"], sp["max_flow_px"], sp["smooth"],
+                            sp.get("alpha", DEFAULT_ALPHA), storage, update,
+                            sp.get("read_flags", 0)) for sp in self.specs]
+        self.ctx = sf_create_batch(cfgs, stream)
+        sf_set_cameras(self.ctx, [sp["camera"] for sp in self.specs])
+
+    def push(self, Ys, rhos, dts):
+        sf_push_frames(self.ctx, Ys, rhos, dts)
+
+    def flow(self, stream, kind=SF_FLOW_W_FRAME, out=None):
+        import torch
+        sp = self.specs[stream]
+        if out is None:
+            out = torch.empty((FLOW_COMPONENTS[kind], sp["rows"], sp["cols"]), dtype=torch.float32,
+                              device="cuda")
+        sf_get_flow_stream(self.ctx, stream, kind, out)
+        return out
+
+    def update_inputs(self, stream, out=None):
+        import torch
+        sp = self.specs[stream]
+        if out is None:
+            out = torch.empty((SF_UPDATE_INPUT_PLANES, sp["rows"], sp["cols"]),
+                              dtype=torch.float32, device="cuda")
+        sf_get_update_inputs(self.ctx, stream, out)
+        return out
+
+    def get_state(self, stream):
+        sp = self.specs[stream]
+        return unpack_state(sf_get_state_stream(self.ctx, stream), sp["rows"], sp["cols"],
+                            sp["levels"])
+
+    def set_learned(self, params, threshold):
+        sf_set_learned(self.ctx, params, threshold)
+
+    def learned_stats(self, reset=False):
+        return sf_learned_stats(self.ctx, reset)
 
     def close(self):
         if self.ctx:

@@ -327,14 +327,14 @@ class Sequence:
 
 
 def _flow_scale(seq_factory: Callable[[float, float], Sequence], target_px: float,
-                rot_share: float) -> tuple:
+                rot_share: float, device="cpu") -> tuple:
     """Scale translation and rotation so that the frame-0 pixel flow reaches target_px,
     with about rot_share of it from rotation (flow is linear in both jointly)."""
-    mt = seq_factory(1.0, 0.0).max_flow_px(0)
-    mr = seq_factory(0.0, 1.0).max_flow_px(0) if rot_share > 0 else 0.0
+    mt = seq_factory(1.0, 0.0).max_flow_px(0, device)
+    mr = seq_factory(0.0, 1.0).max_flow_px(0, device) if rot_share > 0 else 0.0
     kt = (1.0 - rot_share) * target_px / mt if mt > 0 else 0.0
     kr = rot_share * target_px / mr if mr > 0 else 0.0
-    m = seq_factory(kt, kr).max_flow_px(0)
+    m = seq_factory(kt, kr).max_flow_px(0, device)
     return kt * target_px / m, kr * target_px / m
 
 
@@ -387,7 +387,7 @@ def sinusoid_plane_sequence(rows=64, cols=64, n_frames=20, seed=1, dt=1.0,
 
 def box_sequence(rows=512, cols=512, n_frames=100, seed=2, dt=1.0 / 300.0, max_flow_px=8.0,
                  n_boxes=8, depth_range=(2.0, 50.0), depth_noise=0.01, hfov_deg=90.0,
-                 rot_share=0.2, flow_margin=0.85) -> Sequence:
+                 rot_share=0.2, flow_margin=0.85, device="cpu") -> Sequence:
     """Seeded textured boxes and planes inside an enclosing box, a camera with constant
     linear velocity plus sinusoidal angular velocity, max image motion about max_flow_px."""
     rng = np.random.default_rng(seed)
@@ -425,7 +425,7 @@ def box_sequence(rows=512, cols=512, n_frames=100, seed=2, dt=1.0 / 300.0, max_f
         return Sequence(cam, scene, traj, dt, n_frames, depth_noise=depth_noise,
                         noise_seed=seed)
 
-    kt, kr = _flow_scale(make, flow_margin * max_flow_px, rot_share)
+    kt, kr = _flow_scale(make, flow_margin * max_flow_px, rot_share, device)
     return make(kt, kr)
 
 

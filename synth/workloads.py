@@ -22,17 +22,18 @@ WORKLOADS = {
     # 64 x 64, one level, 20 frames, dt = 1: sinusoid-textured tilted plane,
     # rho in [0.2, 1], constant translation, flow <= 1 px
     "plane64": dict(
-        build=lambda: sinusoid_plane_sequence(64, 64, 20, seed=1, dt=1.0),
+        build=lambda device="cpu": sinusoid_plane_sequence(64, 64, 20, seed=1, dt=1.0),
         levels=1, max_flow_px=1.0, smooth=[2], frames=20),
     # 512 x 512, three levels, 100 frames at 300 Hz: eight seeded boxes/planes,
     # constant linear velocity plus sinusoidal rotation, flow up to 8 px, 1 % depth noise
     "boxes512": dict(
-        build=lambda: box_sequence(512, 512, 100, seed=2, dt=1.0 / 300.0, max_flow_px=8.0),
+        build=lambda device="cpu": box_sequence(512, 512, 100, seed=2, dt=1.0 / 300.0,
+                                                max_flow_px=8.0, device=device),
         levels=3, max_flow_px=8.0, smooth=_smooth(3), frames=100),
     # 2048 x 1024, four levels, flow up to 16 px, 200 frames at 200 Hz, ground plane +
     # 30 boxes, forward motion at 15 m/s, 2 % depth noise, open sky (rho = 0)
     "driving2048x1024": dict(
-        build=lambda: driving_sequence(1024, 2048, 200, seed=4),
+        build=lambda device="cpu": driving_sequence(1024, 2048, 200, seed=4, device=device),
         levels=4, max_flow_px=16.0, smooth=_smooth(4), frames=200),
 }
 
@@ -44,7 +45,7 @@ def workload(name: str):
 _MIX_SIZES = (256, 512, 1024)
 
 
-def stream_mix(n_streams: int = 64, seed: int = 3, n_frames: int = 100):
+def stream_mix(n_streams: int = 64, seed: int = 3, n_frames: int = 100, device="cpu"):
     """Batched workload: n_streams independent box scenes of mixed square sizes drawn
     from {256, 512, 1024}; 3 levels (4 for 1024), max flow 4/8/16 px; scene seeds
     1000 + i.  Returns a list of dicts with the builder and filter settings."""
@@ -58,5 +59,6 @@ def stream_mix(n_streams: int = 64, seed: int = 3, n_frames: int = 100):
         out.append(dict(
             size=s, levels=levels, max_flow_px=mf, smooth=_smooth(levels),
             build=(lambda s=s, mf=mf, i=i: box_sequence(s, s, n_frames, seed=1000 + i,
-                                                        dt=1.0 / 300.0, max_flow_px=mf))))
+                                                        dt=1.0 / 300.0, max_flow_px=mf,
+                                                        device=device))))
     return out

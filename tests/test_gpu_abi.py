@@ -41,10 +41,12 @@ def test_config_validation(sf):
     ]
     for cfg in bad:
         assert _code(sf.sf_create, cfg, 0) == sf.SF_ERR_INVALID_ARG, sf.sf_last_error(None)
-    # halo larger than the 64-pixel region, and the learned update without weights
+    # halo larger than the 64-pixel region; the learned update with more than 4 smoothing passes
     assert _code(sf.sf_create, sf.make_config(256, 256, 1, 30.0, [2]), 0) == sf.SF_ERR_UNSUPPORTED
-    assert _code(sf.sf_create, sf.make_config(64, 64, 1, 1.0, [2], update=1), 0) == \
+    assert _code(sf.sf_create, sf.make_config(64, 64, 1, 1.0, [5], update=1), 0) == \
         sf.SF_ERR_UNSUPPORTED
+    assert _code(sf.sf_create, sf.make_config(64, 64, 1, 1.0, [2], update=2), 0) == \
+        sf.SF_ERR_INVALID_ARG
 
 
 def test_call_errors_and_state_rules(sf):

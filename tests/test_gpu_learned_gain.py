@@ -1,0 +1,117 @@
+"""The learned update trained on the GPU beats the plain update on held-out sequences.
+
+Training data: the filter runs seeded box sequences (textured boxes and planes, constant
+linear velocity plus sinusoidal rotation, 1 % depth noise) with every pixel falling back, and
+exports each frame's network inputs; the targets are the corrections that reach the true
+structure flow.  Evaluation: other seeds, the plain and the learned filter side by side, the
+endpoint error against the true flow in pixels per frame."""
+import numpy as np
+import pytest
+
+from gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+
+R, C, H, MF, SMOOTH = 96, 128, 2, 4.0, [2, 4]
+DT = 1.0 / 300.0
+N_FRAMES = 24
+TRAIN_SEEDS = range(300, 308)
+EVAL_SEEDS = range(400, 404)
+
+
+def _seq(seed):
+    from synth.scenes import box_sequence
+    return box_sequence(R, C, N_FRAMES, seed=seed, dt=DT, max_flow_px=MF, device="cuda")
+
+
+def _filter(seq, update, params=None, threshold=-1.0):
+    from paper_2406_18031_amd import sflow
+    cam = seq.camera
+    f = sflow.Filter(R, C, H, MF, SMOOTH, cam.fx, cam.fy, cam.cx, cam.cy, update=update)
+    if update == sflow.SF_UPDATE_LEARNED:
+        f.set_learned(params, threshold)
+    return f
+
+
+def _frames(seq):
+    import torch
+    for k in range(seq.n_frames):
+        fr = seq.frame(k, "cuda")
+        yield (k, fr.Y.to(torch.float32).contiguous(), fr.rho.to(torch.float32).contiguous(),
+               (fr.w_gt * seq.dt).permute(2, 0, 1).to(torch.float32).contiguous())
+
+
+def _collect(seeds, params0):
+    from paper_2406_18031_amd import learned, sflow
+    data = []
+    for s in seeds:
+        seq = _seq(s)
+        f = _filter(seq, sflow.SF_UPDATE_LEARNED, params0, -1.0)
+        for k, Y, rho, w in _frames(seq):
+            f.push(Y, rho, seq.dt)
+            if k >= 1:
+                inp, tgt = learned.sample(f.update_inputs(), w)
+                data.append((inp.clone(), tgt.clone()))
+        f.close()
+    return data
+
+
+def _epe(f, seq, dmu):
+    """mean endpoint error (px/frame) against the truth over frames 4.. of the sequence"""
+    from paper_2406_18031_amd import sflow
+    errs = []
+    for k, Y, rho, w in _frames(seq):
+        f.push(Y, rho, seq.dt)
+        if k >= 4:
+            e = (f.flow(sflow.SF_FLOW_W_FRAME) - w).norm(dim=0) / dmu
+            errs.append(float(e.mean()))
+    return float(np.mean(errs))
+
+
+def test_learned_update_beats_plain():
+    import torch
+    from paper_2406_18031_amd import learned, sflow
+    p0 = learned.init_params(0)
+    log("collecting training data")
+    data = _collect(TRAIN_SEEDS, p0)
+    log(f"  {len(data)} frames of {R}x{C}")
+    g = torch.Generator().manual_seed(0)
+
+    def batches(n, bs=8):
+        for _ in range(n):
+            idx = torch.randperm(len(data), generator=g)[:bs].tolist()
+            yield (torch.cat([data[i][0].reshape(-1) for i in idx]),
+                   torch.cat([data[i][1].reshape(-1) for i in idx]))
+
+    sizes = [(R, C)] * 8
+    params, losses = learned.train(sizes, batches(300), p0, lr=2e-3)
+    params, l2 = learned.train(sizes, batches(100), params, lr=5e-4)
+    losses += l2
+    log(f"  loss {np.mean(losses[:10]):.4f} -> {np.mean(losses[-10:]):.4f}")
+    assert np.mean(losses[-10:]) < np.mean(losses[:10])
+
+    plain_e, learned_e, fb_rate = [], {}, {}
+    thresholds = (float("inf"), 1.0, 0.1)
+    for s in EVAL_SEEDS:
+        seq = _seq(s)
+        probe = _filter(seq, sflow.SF_UPDATE_LEARNED, params, -1.0)
+        k, Y, rho, w = next(_frames(seq))
+        probe.push(Y, rho, seq.dt)
+        probe.push(Y, rho, seq.dt)
+        dmu = probe.update_inputs()[15]
+        probe.close()
+        plain_e.append(_epe(_filter(seq, sflow.SF_UPDATE_PLAIN), seq, dmu))
+        for t in thresholds:
+            f = _filter(seq, sflow.SF_UPDATE_LEARNED, params, t)
+            learned_e.setdefault(t, []).append(_epe(f, seq, dmu))
+            fb, px = f.learned_stats()
+            fb_rate.setdefault(t, []).append(fb / px)
+            f.close()
+    plain = float(np.mean(plain_e))
+    log(f"  plain GT-EPE {plain:.4f} px/frame")
+    best = min(thresholds, key=lambda t: np.mean(learned_e[t]))
+    for t in thresholds:
+        log(f"  learned threshold {t}: GT-EPE {np.mean(learned_e[t]):.4f}, "
+            f"fallback rate {np.mean(fb_rate[t]):.3f}")
+    assert np.mean(learned_e[best]) <= 1.05 * plain
+    assert np.mean(learned_e[best]) < plain
