@@ -110,8 +110,8 @@ def run_gpu(wl_name, steps, warmup, storage=0):
 
 def run_batched(n_streams, steps, warmup, storage=0, frames=6):
     """n_streams independent camera streams of mixed sizes advanced together: one pyramid
-    launch per depth, one level-step launch and one reconstruction launch per depth per
-    frame for all streams.  A step is one frame of every stream plus every stream's output."""
+    launch per depth, one level-step launch and one reconstruction launch per frame for all
+    streams.  A step is one frame of every stream plus every stream's output."""
     import torch
     from paper_2406_18031_amd import sflow
     from synth.workloads import stream_mix
@@ -179,6 +179,57 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
     }
 
 
+def run_learned(n_streams, steps, warmup, frames=6):
+    """The learned update on n_streams 512 x 512 box sequences (3 levels, max flow 8 px),
+    plain and learned side by side on the same frames.  The network's parameters are a fresh
+    initialisation: this measures throughput only (the accuracy of trained parameters is a
+    test's business)."""
+    import torch
+    from paper_2406_18031_amd import learned, sflow
+    from synth.scenes import box_sequence
+
+    specs, Ys, Rs = [], [], []
+    for i in range(n_streams):
+        seq = box_sequence(512, 512, frames, seed=20000 + i, dt=1.0 / 300.0, max_flow_px=8.0,
+                           device="cuda")
+        c = seq.camera
+        specs.append(dict(rows=512, cols=512, levels=3, max_flow_px=8.0, smooth=[2, 4, 4],
+                          camera=(c.fx, c.fy, c.cx, c.cy)))
+        y, r = render_frames(seq, "cuda")
+        Ys.append(y)
+        Rs.append(r)
+        dt = seq.dt
+    out = {}
+    for name, upd in (("plain", sflow.SF_UPDATE_PLAIN), ("learned", sflow.SF_UPDATE_LEARNED)):
+        b = sflow.Batch(specs, update=upd)
+        if upd == sflow.SF_UPDATE_LEARNED:
+            b.set_learned(learned.init_params(0), 1.0)
+        dts = [dt] * n_streams
+
+        def step(k):
+            b.push([y[k % frames] for y in Ys], [r[k % frames] for r in Rs], dts)
+
+        for k in range(warmup):
+            step(k)
+        torch.cuda.synchronize()
+        if upd == sflow.SF_UPDATE_LEARNED:
+            b.learned_stats(reset=True)
+        t0 = time.perf_counter()
+        for k in range(warmup, warmup + steps):
+            step(k)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"aggregate_frames_per_s": n_streams * steps / el,
+                     "ms_per_batch_frame": el / steps * 1e3}
+        if upd == sflow.SF_UPDATE_LEARNED:
+            fb, px = b.learned_stats()
+            out[name]["fallback_rate"] = fb / max(1, px)
+        b.close()
+    out["streams"] = n_streams
+    out["workload"] = "512x512 box sequences, 3 levels, max flow 8 px, untrained network"
+    return out
+
+
 def cpu_baseline(wl_name, budget_s=20.0):
     """The oracle on the host's cores over a bounded sample of the same workload."""
     import numpy as np
@@ -222,6 +273,48 @@ def _finest_dmu(seq):
     return np.sqrt(1 + y * y) / np.sqrt(x * x + y * y + 1) / (c.fx * np.sqrt(xn * xn + y * y + 1))
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_boxes512_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2406_18031_amd", "csrc", "sflow_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per level-step launch from the committed rocprofv3 counter summary (FETCH_SIZE
+    + WRITE_SIZE, scaled by the same counters on a plain copy of known size), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    with open(COUNTERS) as fh:
+        for line in fh:
+            if line.startswith("- ") and " = " in line:
+                k, v = line[2:].split(" = ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def copy_probe(mib: int, reps: int = 20):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "launches": reps + 3, "gbs": 2 * n * 4 * reps / el / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,11 +324,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and batched forms")
     ap.add_argument("--streams", type=int, default=64)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the filter runs on a single device and this build "
               f"has no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     r = run_gpu(args.workload, args.steps, args.warmup, storage=0)
     seq, wl = r["seq"], r["wl"]
@@ -277,7 +375,7 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic() if args.workload == "boxes512" else None,
             "kernel": "k_step (fused level step, all levels in one launch)",
             "kernel_us": step_ms * 1e3,
             "algorithmic_flops": step_flops,
@@ -314,6 +412,10 @@ def main():
             forms[f"batched_{rb['storage']}"] = rb
             print(f"[bench] batched {rb['storage']}: {rb['aggregate_frames_per_s']:.1f} "
                   f"stream-frames/s ({rb['mpix_per_s']:.0f} Mpix/s)", flush=True)
+        rl = run_learned(16, max(5, args.steps // 5), 2)
+        forms["learned_16x512"] = rl
+        print(f"[bench] learned 16x512: {rl['learned']['aggregate_frames_per_s']:.1f} "
+              f"stream-frames/s (plain {rl['plain']['aggregate_frames_per_s']:.1f})", flush=True)
         res["forms"] = forms
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload)

@@ -2,7 +2,7 @@
 //
 // k_step is the hot path: one workgroup owns one output tile of one pyramid level and runs,
 // for that tile, every stage of the level's predictor-update block (Section "Filter
-// Architecture") with the tile plus a halo resident in LDS:
+// Architecture") on the tile plus a halo held on chip:
 //   prediction  N upwind column/row half-steps (Section "Numerical prediction"),
 //   image model 5x5 Gaussian-weighted linear fit as separable passes (eq:img_model),
 //   depth model occlusion-aware one-sided differences (eq:dominant_b1/b2),
@@ -11,11 +11,12 @@
 //   smoothing   N_s passes of the 5x5 average,
 //   rho update  eq:cost_invdepth.
 // The halo is max(N, 2) + 2 N_s pixels per side: each half-step invalidates one pixel on
-// each interior side of the region, each 5x5 pass two.  Column half-steps give every wave
-// whole rows (lane = column), row half-steps whole columns (lane = row), so neighbours along
-// the pass come from lane shuffles and LDS reads within the wave and only a block barrier
-// separates the passes.  Geometry (unit ray, tangent basis, pixel spacing) is recomputed
-// from the pinhole intrinsics in registers instead of being read from memory.
+// each interior side of the region, each 5x5 pass two.  The region (at most 64 x 64) lives in
+// registers: lane l of wave w holds column l of the wave's strip of rows, so column
+// neighbours come from DPP lane shifts and row neighbours from the same lane's registers,
+// with only the strip-boundary rows exchanged through LDS (one barrier per step).  Geometry
+// (unit ray, tangent basis, pixel spacing) is recomputed from the pinhole intrinsics in
+// registers instead of being read from memory.
 #include "sflow_internal.h"
 
 namespace sflow {
@@ -79,9 +80,9 @@ __device__ __forceinline__ float pixel_dmu(const LevelDev& L, int i, int j) {
     const float yy1 = fmaf(y, y, 1.0f);
     const float r2 = fmaf(x, x, yy1);
     const float rinv = rsqrtf(r2);
-    const float fxrn = L.fx * sqrtf(fmaf(xn, xn, yy1));
-    const float q = sqrtf(fmaf(y, y, 1.0f)) * rinv;
-    return q / fxrn;
+    const float fxrn = L.fx * __builtin_amdgcn_sqrtf(fmaf(xn, xn, yy1));
+    const float q = __builtin_amdgcn_sqrtf(fmaf(y, y, 1.0f)) * rinv;
+    return q * __builtin_amdgcn_rcpf(fxrn);
 }
 
 __device__ __forceinline__ float flow_u(const Geo& g, float wx, float wy, float wz) {
@@ -152,8 +153,8 @@ __device__ __forceinline__ void row_geo(const LevelDev& L, int i, float x, float
     const float yy1 = fmaf(y, y, 1.0f);
     const float r2 = fmaf(x, x, yy1);
     rinv = rsqrtf(r2);
-    fxrn = L.fx * sqrtf(fmaf(xn, xn, yy1));
-    const float inv = 1.0f / yy1;
+    fxrn = L.fx * __builtin_amdgcn_sqrtf(fmaf(xn, xn, yy1));
+    const float inv = __builtin_amdgcn_rcpf(yy1);   // 1 ulp reciprocal
     xi = x * inv;
     B = fxrn * (r2 * rinv) * inv;
 }
@@ -181,19 +182,27 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
         float uh = dom_lit ? (larger_next ? um : up) : (larger_next ? up : um);
         if (cfl) uh = __builtin_amdgcn_fmed3f(uh, -fN, fN);
         const float s = grinv[r] * fmaf(x, wx, t);           // <eta, w>
-        // upwind step: f - dt (u_hat D + sigma f s) = c f - |dt u_hat| (f - m), where m is the
-        // upwind neighbour (left if u_hat > 0, else right) and c = 1 - dt sigma s
-        const float ak = fabsf(dt * uh);
+        // upwind step f - dt (u_hat D f + sigma s f) with D the one-sided difference toward
+        // the upwind side, written as k0 f + ap f_left - am f_right with ap = dt max(u_hat, 0),
+        // am = dt min(u_hat, 0), k0 = 1 - dt sigma s - ap + am (no source term for the image).
+        // At the image border the missing neighbour equals the pixel itself, so its weight
+        // moves into k0, i.e. the coefficient is dropped.
+        const float du = dt * uh;
+        float ap = fmaxf(du, 0.0f), am = fminf(du, 0.0f);
+        if (BORDER) {
+            ap = at_left ? 0.0f : ap;
+            am = at_right ? 0.0f : am;
+        }
         const float c = fmaf(-dtsig, s, 1.0f);
-        const bool back = uh > 0.0f;
+        const float k0 = (c - ap) + am;
+        const float k1 = (1.0f - ap) + am;
 #pragma unroll
         for (int k = 0; k < NF; ++k) {
             const float f = F[r][k];
-            const float db = f - nb_prev<BORDER>(f, at_left);
-            const float df = f - nb_next<BORDER>(f, at_right);
-            const float d = back ? db : df;
-            const float cf = (NF == 8 && k == 7) ? f : c * f;   // the image has no source term
-            F[r][k] = fmaf(-ak, d, cf);
+            const float fm = dpp_prev(f);
+            const float fp = dpp_next(f);
+            const float kk = (NF == 8 && k == 7) ? k1 : k0;
+            F[r][k] = fmaf(kk, f, fm * ap - fp * am);
         }
     }
 }
@@ -328,16 +337,19 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
                 if (cfl) vh = __builtin_amdgcn_fmed3f(vh, -fN, fN);
                 const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
-                const float ak = fabsf(dt * vh);
+                // same upwind form as the column pass, neighbours above and below
+                const float dv = dt * vh;
+                const float ap = top_b ? 0.0f : fmaxf(dv, 0.0f);
+                const float am = bot_b ? 0.0f : fminf(dv, 0.0f);
                 const float c = fmaf(-dtsig, s, 1.0f);
-                const bool back = vh > 0.0f;
+                const float k0 = (c - ap) + am;
+                const float k1 = (1.0f - ap) + am;
 #pragma unroll
                 for (int k = 0; k < NF; ++k) {
-                    const float fm = top_b ? cur[k] : prev[k];
-                    const float fp = bot_b ? cur[k] : (r + 1 < RPW ? F[r + 1 < RPW ? r + 1 : r][k] : below[k]);
-                    const float d = cur[k] - (back ? fm : fp);
-                    const float cf = (!TOP && k == 7) ? cur[k] : c * cur[k];
-                    F[r][k] = fmaf(-ak, d, cf);
+                    const float fm = prev[k];
+                    const float fp = r + 1 < RPW ? F[r + 1 < RPW ? r + 1 : r][k] : below[k];
+                    const float kk = (!TOP && k == 7) ? k1 : k0;
+                    F[r][k] = fmaf(-am, fp, fmaf(ap, fm, kk * cur[k]));
                 }
             }
 #pragma unroll
@@ -425,11 +437,11 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
             // tangent basis and spacing at (i, j)
             const float rinv = grinv[r];
             const float ex = x * rinv, ey = gy[r] * rinv, ez = rinv;
-            const float q = sqrtf(fmaf(gy[r], gy[r], 1.0f)) * rinv;   // sqrt(1 - eta_x^2)
-            const float iq = 1.0f / q;
+            const float q = __builtin_amdgcn_sqrtf(fmaf(gy[r], gy[r], 1.0f)) * rinv;   // sqrt(1 - eta_x^2)
+            const float iq = __builtin_amdgcn_rcpf(q);
             const float b1x = q, b1y = -ex * ey * iq, b1z = -ex * ez * iq;
             const float b2y = ez * iq, b2z = -ey * iq;
-            const float dmu = q / gfxrn[r];
+            const float dmu = q * __builtin_amdgcn_rcpf(gfxrn[r]);
             const float aYx = b1x * d1, aYy = fmaf(b1y, d1, b2y * d2), aYz = fmaf(b1z, d1, b2z * d2);
             float aRx = 0.0f, aRy = 0.0f, aRz = 0.0f, cR = 0.0f;
             const size_t gs = (size_t)i * L.pitch + j;
@@ -443,7 +455,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 cR = rc - rprior;
             }
             const float cY = Yh - Yprior;
-            const float idmu = 1.0f / dmu;
+            const float idmu = gfxrn[r] * iq;
             constexpr int KX = TOP ? 0 : 3;
             const float x0 = F[r][KX] * idmu, y0 = F[r][KX + 1] * idmu, z0 = F[r][KX + 2] * idmu;
             const float dmu2 = dmu * dmu;
@@ -458,15 +470,17 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                         cz_ = aYx * aRy - aYy * aRx;
             const float cross2 = fmaf(cx_, cx_, fmaf(cy_, cy_, cz_ * cz_));   // aa bb - ab^2
             const float det = fmaf(sg3, sg3 + G1 * aa2 + G2 * bb, G1 * G2 * cross2);
-            const float al = -G1 * fmaf(res1, sg3, G2 * (res1 * bb - ab * res2)) / det;
-            const float be = -G2 * fmaf(res2, sg3, G1 * (res2 * aa2 - ab * res1)) / det;
+            const float idet = __builtin_amdgcn_rcpf(det);   // det >= gamma_3^2 > 0
+            const float al = -G1 * fmaf(res1, sg3, G2 * (res1 * bb - ab * res2)) * idet;
+            const float be = -G2 * fmaf(res2, sg3, G1 * (res2 * aa2 - ab * res1)) * idet;
             const float rpred = F[r][KR];
             const float px0 = F[r][KX], py0 = F[r][KX + 1], pz0 = F[r][KX + 2];
             F[r][KX] = fmaf(al, aYx, fmaf(be, aRx, x0)) * dmu;
             F[r][KX + 1] = fmaf(al, aYy, fmaf(be, aRy, y0)) * dmu;
             F[r][KX + 2] = fmaf(al, aYz, fmaf(be, aRz, z0)) * dmu;
             if (i >= ti0 && i < ti1 && tcol) {
-                const float rn = rv ? (L.g4 * rc + L.g5 * rpred) / (L.g4 + L.g5) : rpred;
+                const float rn = rv ? (L.g4 * rc + L.g5 * rpred) * __builtin_amdgcn_rcpf(L.g4 + L.g5)
+                                    : rpred;
                 stv(Rout, gs, rn);
                 stv(Yout, gs, Yh);
                 if (L.learned) {
@@ -655,29 +669,101 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
     }
 }
 
-// reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[parity]
+// Coarse-to-fine reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h of every level
+// below the top, in state[parity], in one launch.  A block owns a kRecTile x kRecTile tile of
+// the finest level; it computes, coarsest first, the patch of every lower level that the tile
+// depends on (each level's patch from the one above, held in LDS as the values the state
+// store will hold), and stores the level-h pixels whose finest-level image (2^h i, 2^h j)
+// lies in its tile, so every pixel is stored once and every block sees the same values.
+constexpr int kRecTile = kReconstructTile;
+constexpr int kRecPatch = kRecTile / 2 + 1;       // rows/cols of a patch at level >= 1
+
+template <typename T> __device__ __forceinline__ float stored(float v);
+template <> __device__ __forceinline__ float stored<float>(float v) { return v; }
+template <> __device__ __forceinline__ float stored<__half>(float v) {
+    return __half2float(__float2half(v));
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
-    int e, i, j;
-    if (!elem_pixel(a, e, i, j)) return;
-    const LevelDev& L = a.lv[e];
-    const LevelDev& U = a.lv[L.parent];
+__global__ void __launch_bounds__(256) k_reconstruct(ElemArgs a) {
+    __shared__ float P[2][3][kRecPatch * kRecPatch];
+    const int b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
+    const int e0 = a.ent[k];
+    const LevelDev& L0 = a.lv[e0];
+    const int t = b - a.blk[k];
+    const int tiles_x = (L0.cols + kRecTile - 1) / kRecTile;
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int ti0 = ty * kRecTile, tj0 = tx * kRecTile;
+    // patch bounds per level, finest first, up to the level below the top
+    int ra[kMaxLevels], rb[kMaxLevels], ca[kMaxLevels], cb[kMaxLevels];
+    int nl = 0;                                     // levels below the top
+    {
+        int e = e0;
+        ra[0] = ti0;
+        rb[0] = min(ti0 + kRecTile, L0.rows);
+        ca[0] = tj0;
+        cb[0] = min(tj0 + kRecTile, L0.cols);
+        while (!a.lv[e].top) {
+            const LevelDev& U = a.lv[a.lv[e].parent];
+            if (nl + 1 < kMaxLevels) {
+                ra[nl + 1] = ra[nl] >> 1;
+                rb[nl + 1] = min(((rb[nl] - 1) >> 1) + 2, U.rows);
+                ca[nl + 1] = ca[nl] >> 1;
+                cb[nl + 1] = min(((cb[nl] - 1) >> 1) + 2, U.cols);
+            }
+            e = a.lv[e].parent;
+            ++nl;
+        }
+    }
     const int q = a.parity;
-    const int i0 = i >> 1, j0 = j >> 1;
-    const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
-    const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
-    const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
-    const float w10 = fi * (1.0f - fj), w11 = fi * fj;
-    const float uin = flow_in_scale<T>(U);
-    const float lin = flow_in_scale<T>(L);
-    const float lout = flow_out_scale<T>(L);
-    const size_t go = (size_t)i * L.pitch + j;
-    for (int k = 0; k < 3; ++k) {
-        const T* W = (const T*)U.w[q][k];
-        const float c = w00 * ldv(W, (size_t)i0 * U.pitch + j0) + w01 * ldv(W, (size_t)i0 * U.pitch + j1) +
-                        w10 * ldv(W, (size_t)i1 * U.pitch + j0) + w11 * ldv(W, (size_t)i1 * U.pitch + j1);
-        const float v = c * uin + ldv((const T*)L.dw[q][k], go) * lin;
-        stv((T*)L.w[q][k], go, v * lout);
+    for (int h = nl - 1; h >= 0; --h) {
+        const LevelDev& L = a.lv[e0 + h];
+        const LevelDev& U = a.lv[L.parent];
+        const bool parent_top = h == nl - 1;
+        const float uin = flow_in_scale<T>(U);
+        const float lin = flow_in_scale<T>(L);
+        const float lout = flow_out_scale<T>(L);
+        const int pw = cb[h + 1 < kMaxLevels ? h + 1 : h] - ca[h + 1 < kMaxLevels ? h + 1 : h];
+        const int pa = ra[h + 1 < kMaxLevels ? h + 1 : h], pc = ca[h + 1 < kMaxLevels ? h + 1 : h];
+        const float* src = P[(h + 1) & 1][0];
+        float* dst = P[h & 1][0];
+        const int w = cb[h] - ca[h];
+        const int n = (rb[h] - ra[h]) * w;
+        for (int p = threadIdx.x; p < n; p += 256) {
+            const int i = ra[h] + p / w;
+            const int j = ca[h] + p % w;
+            const int i0 = i >> 1, j0 = j >> 1;
+            const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
+            const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
+            const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
+            const float w10 = fi * (1.0f - fj), w11 = fi * fj;
+            const size_t go = (size_t)i * L.pitch + j;
+            const bool own = h == 0 || (((i << h) >= ti0) && ((i << h) < ti0 + kRecTile) &&
+                                        ((j << h) >= tj0) && ((j << h) < tj0 + kRecTile));
+            for (int c = 0; c < 3; ++c) {
+                float p00, p01, p10, p11;
+                if (parent_top) {
+                    const T* W = (const T*)U.w[q][c];
+                    p00 = ldv(W, (size_t)i0 * U.pitch + j0);
+                    p01 = ldv(W, (size_t)i0 * U.pitch + j1);
+                    p10 = ldv(W, (size_t)i1 * U.pitch + j0);
+                    p11 = ldv(W, (size_t)i1 * U.pitch + j1);
+                } else {
+                    const float* S = src + c * kRecPatch * kRecPatch;
+                    p00 = S[(i0 - pa) * pw + (j0 - pc)];
+                    p01 = S[(i0 - pa) * pw + (j1 - pc)];
+                    p10 = S[(i1 - pa) * pw + (j0 - pc)];
+                    p11 = S[(i1 - pa) * pw + (j1 - pc)];
+                }
+                const float cc = w00 * p00 + w01 * p01 + w10 * p10 + w11 * p11;
+                const float v = cc * uin + ldv((const T*)L.dw[q][c], go) * lin;
+                if (own) stv((T*)L.w[q][c], go, v * lout);
+                if (h > 0) dst[c * kRecPatch * kRecPatch + p] = stored<T>(v * lout);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -902,9 +988,9 @@ hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds, 
 hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
