@@ -191,23 +191,27 @@ sf_status sf_kernel_times(sf_ctx ctx, double* ms3, int64_t* launches3, int32_t r
 /* ---- learned update ----------------------------------------------------------------------
  * An extension beyond the paper, which uses the least-squares update of Section "State
  * update" at every level.  With update = SF_UPDATE_LEARNED, at the finest level of every
- * stream a convolutional network (3x3 kernels, 6 -> 16 -> 16 -> 16 -> 3 channels, ReLU after
- * the first three layers, zero padding; BF16 operands, FP32 accumulation) gives a correction
- * c (3 values, pixels per frame) of the predicted field x0 (the flow at a top level, the
- * increment over the parent's flow below it): x_net = x0 + dmu * c.  Its inputs per pixel are
- * Y_prior - 1/2, Y_new - 1/2, 4 rho (0 where missing) and x0 / dmu / 4 (3), where Y_prior is
- * the predicted smoothed image and Y_new the new one (Section "State update").
- * Per pixel, x_net replaces the least-squares solution x_ls unless the least-squares cost of
- * the step, G1 (aY.d)^2 + G2 (aR.d)^2 + gamma_3 |d|^2 with d = (x_net - x_ls) / dmu (the cost
- * increase over its minimum at x_ls, in pixel units), exceeds `threshold`; then x_ls is kept
- * (a "fallback").  Smoothing and the rest of the frame are unchanged.  A threshold < 0 makes
- * every pixel fall back, which gives exactly the plain update.
+ * stream a convolutional network (3x3 kernels, 9 -> 16 -> 16 -> 16 -> 3 channels, ReLU after
+ * the first three layers, zero padding; BF16 operands, FP32 accumulation) corrects the output
+ * flow: with x_ls the solution of the update and S the level's N_s passes of 5x5 averaging
+ * (so that S(x_ls) is the level's new state), sf_get_flow reports the flow of
+ * S(x_ls) + dmu * c, where c (3 values, pixels per frame) is the network's output.  The
+ * filter's state, and so its recurrence, stay those of the plain update.  The network's
+ * inputs per pixel are Y_prior - 1/2, Y_new - 1/2, 4 rho (0 where missing), x0 / dmu / 4 (3)
+ * and x_ls / dmu / 4 (3), where Y_prior is the predicted smoothed image, Y_new the new one and
+ * x0 the predicted field (the flow at a top level, the increment over the parent's flow
+ * below it; Section "State update").
+ * Per pixel, c is applied unless the least-squares cost of the step,
+ * G1 (aY.c)^2 + G2 (aR.c)^2 + gamma_3 |c|^2 (in pixel units, the cost increase a step c away
+ * from the minimum x_ls), exceeds `threshold` or is not finite (a "fallback": the plain
+ * flow).  A threshold < 0 makes every pixel fall back, which gives exactly the plain
+ * update.  sf_get_state / sf_set_state carry the state only, not the correction.
  *
  * The parameters are FP32, SF_LEARNED_PARAMS values: per layer l = 0..3 the weights
  * W[3][3][cin][cout] (tap row dy+1, tap column dx+1, input channel, output channel;
  * out[p] = b + sum W[dy+1][dx+1][c][:] in[p + (dy, dx)][c]) followed by the bias b[cout]. */
-#define SF_LEARNED_PARAMS 5955
-#define SF_UPDATE_INPUT_PLANES 16
+#define SF_LEARNED_PARAMS 6387
+#define SF_UPDATE_INPUT_PLANES 22
 
 /* Load parameters (host, SF_LEARNED_PARAMS finite floats) and the fallback threshold (not
  * NaN; +inf never falls back); synchronises the stream.  SF_ERR_STATE on a plain context. */
@@ -216,16 +220,16 @@ sf_status sf_set_learned(sf_ctx ctx, const float* params, size_t n, float thresh
 sf_status sf_learned_stats(sf_ctx ctx, int64_t* fallbacks, int64_t* pixels, int32_t reset);
 /* Training data of the last frame of one stream (finest level): writes
  * SF_UPDATE_INPUT_PLANES float32 planes of rows x cols to the device pointer out: the network
- * inputs (6), x0 (3), x_ls (3), the parent's reconstructed flow (3; 0 at a top level) and dmu
- * (1).  Flows are in rad/frame, so the correction that reaches a flow w is
- * (w - parent - x0) / dmu.  SF_ERR_STATE before the second frame. */
+ * inputs (9), x0 (3), x_ls (3), S(x_ls) (3), the parent's reconstructed flow (3; 0 at a top
+ * level) and dmu (1).  Flows are in rad/frame, so the network output that reaches a flow w is
+ * (w - parent - S(x_ls)) / dmu.  SF_ERR_STATE before the second frame. */
 sf_status sf_get_update_inputs(sf_ctx ctx, int32_t stream, float* out);
 
 /* ---- training the learned update's network --------------------------------------------------
  * A network object runs the network above on a fixed list of up to 64 images (sizes given at
  * creation, each at most 2^26 pixels, 2^27 in total), on the caller's HIP stream.  Image
  * tensors are device float32, the images one after the other, each planar [C][rows][cols]
- * (C = 6 for inputs, 3 for outputs and targets).  Every call synchronises the stream except
+ * (C = 9 for inputs, 3 for outputs and targets).  Every call synchronises the stream except
  * sf_net_forward. */
 typedef struct sf_net_s* sf_net;
 sf_status sf_net_create(const int32_t* rows, const int32_t* cols, int32_t n_images,
@@ -234,12 +238,15 @@ sf_status sf_net_create(const int32_t* rows, const int32_t* cols, int32_t n_imag
 sf_status sf_net_set_params(sf_net net, const float* params, size_t n);
 sf_status sf_net_get_params(sf_net net, float* params, size_t n);
 sf_status sf_net_forward(sf_net net, const float* in, float* out);
-/* One step: forward, the loss mean over all pixels of sqrt(|out - target|^2 + 1e-6), its
+/* One step: forward, the loss mean over all pixels of sqrt(|out - target|^2 + eps^2), its
  * gradient by backpropagation, and, when lr > 0, one Adam step (beta 0.9, 0.999, eps 1e-8)
  * on the parameters.  loss_out (host, 1 float) and grad_out (host, SF_LEARNED_PARAMS floats,
  * the gradient at the parameters before the step) may be NULL. */
 sf_status sf_net_train_step(sf_net net, const float* in, const float* target, float lr,
                             float* loss_out, float* grad_out);
+/* the loss's eps (pixels, > 0; default 1e-3: close to the endpoint error itself; about 1
+ * makes the loss quadratic for errors below a pixel) */
+sf_status sf_net_set_loss(sf_net net, float eps);
 sf_status sf_net_destroy(sf_net net);
 const char* sf_net_last_error(sf_net net);
 

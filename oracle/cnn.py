@@ -1,11 +1,13 @@
 """FP64 oracle of the learned update's network (test infrastructure only).
 
-A 4-layer 3x3 convolutional network, 6 -> 16 -> 16 -> 16 -> 3 channels, ReLU after the
+A 4-layer 3x3 convolutional network, 9 -> 16 -> 16 -> 16 -> 3 channels, ReLU after the
 first three layers, zero padding at the image border ("same" size).  It maps per-pixel
-update inputs to a correction of the predicted flow (see the learned form in the library):
+update inputs to a refinement of the smoothed least-squares solution of the update step (the
+learned form of the library):
 
-    inputs  (6): Y_prev - 1/2, Y_new - 1/2, 4 rho_meas (0 where missing), x0/dmu / 4 (3)
-    output  (3): correction in pixels per frame, x = x0 + dmu * out
+    inputs  (9): Y_prev - 1/2, Y_new - 1/2, 4 rho_meas (0 where missing),
+                 x0 / dmu / 4 (3), x_ls / dmu / 4 (3)
+    output  (3): correction in pixels per frame, x = S(x_ls) + dmu * out
 
 Layout: images are (H, W, C) arrays; weights W[l] are (3, 3, C_in, C_out) indexed by the
 tap offset (dy + 1, dx + 1): out[p] = b + sum_{dy,dx,c} W[dy+1, dx+1, c, :] in[p + (dy, dx), c].
@@ -15,10 +17,10 @@ from __future__ import annotations
 
 import numpy as np
 
-CHANNELS = (6, 16, 16, 16, 3)
+CHANNELS = (9, 16, 16, 16, 3)
 EPS = 1e-3
-IN_SHIFT = np.array([-0.5, -0.5, 0.0, 0.0, 0.0, 0.0])
-IN_SCALE = np.array([1.0, 1.0, 4.0, 0.25, 0.25, 0.25])
+IN_SHIFT = np.array([-0.5, -0.5, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+IN_SCALE = np.array([1.0, 1.0, 4.0, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25])
 
 
 def init_params(seed: int = 0):
@@ -100,7 +102,8 @@ def backward(dout: np.ndarray, acts, pres, params):
     return grads
 
 
-def normalise_inputs(Yprev, Ynew, rho, x0_px):
+def normalise_inputs(Yprev, Ynew, rho, x0_px, xls_px):
     rho = np.where(np.isnan(rho), 0.0, rho)
-    x = np.concatenate([Yprev[..., None], Ynew[..., None], rho[..., None], x0_px], axis=-1)
+    x = np.concatenate([Yprev[..., None], Ynew[..., None], rho[..., None], x0_px, xls_px],
+                       axis=-1)
     return (x + IN_SHIFT) * IN_SCALE

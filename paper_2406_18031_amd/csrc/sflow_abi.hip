@@ -522,7 +522,7 @@ sf_status sf_kernel_times(sf_ctx c, double* ms3, int64_t* launches3, int32_t res
 static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias) {
     PackArgs p{};
     p.params = params;
-    static const int ch[5] = {6, 16, 16, 16, 3};
+    static const int ch[5] = {kCnnInputs, 16, 16, 16, 3};
     int off = 0;
     for (int l = 0; l < kCnnLayers; ++l) {
         p.cin[l] = ch[l];
@@ -541,7 +541,7 @@ static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias
 // network on the finest level of every stream, then the per-pixel choice, smoothing and store
 static sf_status run_learned(sf_ctx c, int q) {
     const int P = c->segs.total;
-    HIP_TRY(c, launch_pack_inputs(c->lbuf + (size_t)kLearnIn * P, 6, P, c->act[0], c->stream));
+    HIP_TRY(c, launch_pack_inputs(c->lbuf + (size_t)kLearnIn * P, kCnnInputs, P, c->act[0], c->stream));
     for (int l = 0; l < kCnnLayers; ++l) {
         ConvArgs a{};
         a.segs = c->segs;
@@ -755,6 +755,7 @@ struct BlobHeader {
     int64_t frames;
 };
 static_assert(sizeof(BlobHeader) == 32, "blob header is 32 bytes");
+static_assert(kLearnInputs == kCnnInputs, "the step kernel writes the network's inputs");
 static const uint32_t kMagic = 0x54535346u;   // 'SFST'
 
 static size_t blob_bytes(sf_ctx c, int s) {

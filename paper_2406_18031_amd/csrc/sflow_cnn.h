@@ -8,7 +8,8 @@ namespace sflow {
 
 constexpr int kCnnMaxSegs = 64;
 constexpr int kCnnLayers = 4;
-constexpr int kCnnParams = 5955;   // 6*16*9+16 + 2*(16*16*9+16) + 16*3*9+3
+constexpr int kCnnInputs = 9;
+constexpr int kCnnParams = 6387;   // 9*16*9+16 + 2*(16*16*9+16) + 16*3*9+3
 
 // A list of images stored one after the other; image k's pixels start at base[k] (a
 // multiple of 16); total = padded end of the last image.

@@ -1,5 +1,5 @@
 // The learned update's network on gfx950: a 4-layer 3x3 convolutional network
-// (6 -> 16 -> 16 -> 16 -> 3 channels, ReLU after the first three layers, zero padding) in
+// (9 -> 16 -> 16 -> 16 -> 3 channels, ReLU after the first three layers, zero padding) in
 // BF16 on the matrix cores with FP32 accumulation, and the kernels that train it.
 //
 // Activations are NHWC with 16 BF16 channels per pixel (32 bytes; unused channels are 0),

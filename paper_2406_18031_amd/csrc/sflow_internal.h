@@ -22,8 +22,11 @@ constexpr int kMaxStreams = 64;      // camera streams per context
 // Planes of the learned-update buffers of a finest level: network inputs (6), prior x0 (3),
 // least-squares solution (3), cost terms a_Y (3), a_rho (3), G1, G2 (2) and the network's
 // output (3), each `ltotal` floats.
-constexpr int kLearnIn = 0, kLearnX0 = 6, kLearnXP = 9, kLearnFB = 12, kLearnOut = 20;
-constexpr int kLearnPlanes = 23;
+constexpr int kLearnInputs = 9;
+constexpr int kLearnIn = 0, kLearnX0 = 9, kLearnXP = 12, kLearnFB = 15, kLearnOut = 23;
+constexpr int kLearnXS = 26;      // smoothed least-squares solution (the state)
+constexpr int kLearnCorr = 29;    // applied correction, rad/frame (0 where it fell back)
+constexpr int kLearnPlanes = 32;
 constexpr int kElemBlock = 256;      // threads (pixels) per block of the per-pixel kernels
 
 // Parameters of one pyramid level of one camera stream ("entry"), uploaded to device memory

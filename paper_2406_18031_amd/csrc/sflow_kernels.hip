@@ -494,6 +494,9 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                     lb[(kLearnIn + 3) * P] = x0 * 0.25f;
                     lb[(kLearnIn + 4) * P] = y0 * 0.25f;
                     lb[(kLearnIn + 5) * P] = z0 * 0.25f;
+                    lb[(kLearnIn + 6) * P] = F[r][KX] * idmu * 0.25f;
+                    lb[(kLearnIn + 7) * P] = F[r][KX + 1] * idmu * 0.25f;
+                    lb[(kLearnIn + 8) * P] = F[r][KX + 2] * idmu * 0.25f;
                     lb[(kLearnX0 + 0) * P] = px0;
                     lb[(kLearnX0 + 1) * P] = py0;
                     lb[(kLearnX0 + 2) * P] = pz0;
@@ -666,6 +669,7 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
     for (int k = 0; k < 3; ++k) {
         stv((T*)L.w[0][k], go, 0.0f);
         if (!L.top) stv((T*)L.dw[0][k], go, 0.0f);
+        if (L.learned) L.lbuf[L.lbase + (size_t)(kLearnCorr + k) * L.ltotal + (size_t)i * L.cols + j] = 0.0f;
     }
 }
 
@@ -684,8 +688,10 @@ template <> __device__ __forceinline__ float stored<__half>(float v) {
     return __half2float(__float2half(v));
 }
 
+constexpr int kRecThreads = kRecTile * kRecTile;   // one finest-level pixel per thread
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_reconstruct(ElemArgs a) {
+__global__ void __launch_bounds__(kRecThreads) k_reconstruct(ElemArgs a) {
     __shared__ float P[2][3][kRecPatch * kRecPatch];
     const int b = blockIdx.x;
     int k = 0;
@@ -731,7 +737,7 @@ __global__ void __launch_bounds__(256) k_reconstruct(ElemArgs a) {
         float* dst = P[h & 1][0];
         const int w = cb[h] - ca[h];
         const int n = (rb[h] - ra[h]) * w;
-        for (int p = threadIdx.x; p < n; p += 256) {
+        for (int p = threadIdx.x; p < n; p += kRecThreads) {
             const int i = ra[h] + p / w;
             const int j = ca[h] + p % w;
             const int i0 = i >> 1, j0 = j >> 1;
@@ -783,9 +789,16 @@ __global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
         return;
     }
     const float fs = flow_in_scale<T>(L);
-    const float wx = ldv((const T*)L.w[q][0], go) * fs;
-    const float wy = ldv((const T*)L.w[q][1], go) * fs;
-    const float wz = ldv((const T*)L.w[q][2], go) * fs;
+    float wx = ldv((const T*)L.w[q][0], go) * fs;
+    float wy = ldv((const T*)L.w[q][1], go) * fs;
+    float wz = ldv((const T*)L.w[q][2], go) * fs;
+    if (L.learned) {   // the learned update's correction of the output
+        const float* lb = L.lbuf + L.lbase + o;
+        const size_t P = (size_t)L.ltotal;
+        wx += lb[kLearnCorr * P];
+        wy += lb[(kLearnCorr + 1) * P];
+        wz += lb[(kLearnCorr + 2) * P];
+    }
     if (a.kind == SF_FLOW_W_RAD_S || a.kind == SF_FLOW_W_FRAME) {
         const float m = a.kind == SF_FLOW_W_RAD_S ? a.inv_dt : 1.0f;
         out[o] = wx * m;
@@ -804,9 +817,11 @@ __global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// learned update: per pixel, the network's flow x0 + dmu * out unless its increase of the
-// least-squares cost over the least-squares solution exceeds the threshold; then the level's
-// N_s passes of 5x5 averaging (same order of operations as in k_step) and the state store.
+// learned update: the level's N_s passes of 5x5 averaging of the least-squares solution x_ls
+// (same order of operations as in k_step) and the state store, as in the plain update; then,
+// per pixel, the network's correction dmu * c of the output flow, kept unless its
+// least-squares cost G1 (aY.c)^2 + G2 (aR.c)^2 + g3 |c|^2 exceeds the threshold (or is not
+// finite).  The correction is applied to the output (k_output), not fed back into the state.
 // One block = 32 x 32 output pixels plus a halo of 2 N_s (N_s <= 4).
 // ------------------------------------------------------------------------------------------
 constexpr int kCombTile = 32;
@@ -836,32 +851,14 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
     if (threadIdx.x == 0) nfb = 0;
     __syncthreads();
     const size_t P = (size_t)L.ltotal;
-    const float* lb = L.lbuf + L.lbase;
-    unsigned int myfb = 0;
+    float* lb = L.lbuf + L.lbase;
     for (int q = threadIdx.x; q < (vi1 - vi0) * (vj1 - vj0); q += 256) {
         const int i = vi0 + q / (vj1 - vj0);
         const int j = vj0 + q % (vj1 - vj0);
         const size_t p = (size_t)i * C + j;
-        const float dmu = pixel_dmu(L, i, j);
-        float xc[3], xp[3], d[3];
-        for (int c = 0; c < 3; ++c) {
-            xp[c] = lb[(kLearnXP + c) * P + p];
-            xc[c] = fmaf(dmu, lb[(kLearnOut + c) * P + p], lb[(kLearnX0 + c) * P + p]);
-            d[c] = (xc[c] - xp[c]) / dmu;
-        }
-        const float eY = lb[(kLearnFB + 0) * P + p] * d[0] + lb[(kLearnFB + 1) * P + p] * d[1] +
-                         lb[(kLearnFB + 2) * P + p] * d[2];
-        const float eR = lb[(kLearnFB + 3) * P + p] * d[0] + lb[(kLearnFB + 4) * P + p] * d[1] +
-                         lb[(kLearnFB + 5) * P + p] * d[2];
-        const float cost = lb[(kLearnFB + 6) * P + p] * eY * eY +
-                           lb[(kLearnFB + 7) * P + p] * eR * eR +
-                           L.g3 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-        const bool fb = !(cost <= a.threshold);     // NaN falls back too
         const int li = (i - gi0) * RW + (j - gj0);
-        for (int c = 0; c < 3; ++c) X[c][li] = fb ? xp[c] : xc[c];
-        if (fb && i >= ti0 && i < ti1 && j >= tj0 && j < tj1) ++myfb;
+        for (int c = 0; c < 3; ++c) X[c][li] = lb[(kLearnXP + c) * P + p];
     }
-    if (myfb) atomicAdd(&nfb, myfb);
     __syncthreads();
     for (int sp = 1; sp <= Ns; ++sp) {
         const int rad = 2 * (Ns - sp);
@@ -896,22 +893,42 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
     }
     const float os = flow_out_scale<T>(L);
     const int q2 = a.parity;
+    unsigned int myfb = 0;
     for (int q = threadIdx.x; q < (ti1 - ti0) * (tj1 - tj0); q += 256) {
         const int i = ti0 + q / (tj1 - tj0);
         const int j = tj0 + q % (tj1 - tj0);
+        const size_t p = (size_t)i * C + j;
         const size_t go = (size_t)i * L.pitch + j;
         const int li = (i - gi0) * RW + (j - gj0);
+        float d[3];
+        for (int c = 0; c < 3; ++c) d[c] = lb[(kLearnOut + c) * P + p];   // pixels per frame
+        const float eY = lb[(kLearnFB + 0) * P + p] * d[0] + lb[(kLearnFB + 1) * P + p] * d[1] +
+                         lb[(kLearnFB + 2) * P + p] * d[2];
+        const float eR = lb[(kLearnFB + 3) * P + p] * d[0] + lb[(kLearnFB + 4) * P + p] * d[1] +
+                         lb[(kLearnFB + 5) * P + p] * d[2];
+        const float cost = lb[(kLearnFB + 6) * P + p] * eY * eY +
+                           lb[(kLearnFB + 7) * P + p] * eR * eR +
+                           L.g3 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const bool fb = !(cost <= a.threshold) || !isfinite(cost);   // NaN and inf fall back
+        myfb += fb ? 1u : 0u;
+        const float dmu = pixel_dmu(L, i, j);
         for (int c = 0; c < 3; ++c) {
+            const float xs = X[c][li];
+            lb[(kLearnXS + c) * P + p] = xs;
+            lb[(kLearnCorr + c) * P + p] = fb ? 0.0f : dmu * d[c];
             T* dst = (T*)(L.top ? L.w[q2][c] : L.dw[q2][c]);
-            stv(dst, go, X[c][li] * os);
+            stv(dst, go, xs * os);
         }
     }
+    if (myfb) atomicAdd(&nfb, myfb);
+    __syncthreads();
     if (threadIdx.x == 0 && nfb) atomicAdd(a.fallbacks, (unsigned long long)nfb);
 }
 
-// Learned-update training data of one stream's finest level, after its frame: 16 float32
-// planes [network inputs (6), prior (3), least-squares solution (3), parent flow (3), dmu],
-// flows in the level's field units (rad/frame; the increment at a level with a parent).
+// Learned-update training data of one stream's finest level, after its frame: 22 float32
+// planes [network inputs (9), prior x0 (3), least-squares solution x_ls (3), smoothed x_ls (3),
+// parent flow (3), dmu], flows in the level's field units (rad/frame; the increment at a level
+// with a parent).
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     int e, i, j;
@@ -921,7 +938,8 @@ __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     const size_t o = (size_t)i * L.cols + j;
     const size_t P = (size_t)L.ltotal;
     const float* lb = L.lbuf + L.lbase + o;
-    for (int k = 0; k < 12; ++k) a.out[k * npx + o] = lb[k * P];
+    for (int k = 0; k < kLearnFB; ++k) a.out[k * npx + o] = lb[k * P];
+    for (int k = 0; k < 3; ++k) a.out[(kLearnFB + k) * npx + o] = lb[(kLearnXS + k) * P];
     float base[3] = {0.0f, 0.0f, 0.0f};
     if (!L.top) {
         const LevelDev& U = a.lv[L.parent];
@@ -939,8 +957,8 @@ __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
                       uin;
         }
     }
-    for (int k = 0; k < 3; ++k) a.out[(12 + k) * npx + o] = base[k];
-    a.out[15 * npx + o] = pixel_dmu(L, i, j);
+    for (int k = 0; k < 3; ++k) a.out[(kLearnFB + 3 + k) * npx + o] = base[k];
+    a.out[(kLearnFB + 6) * npx + o] = pixel_dmu(L, i, j);
 }
 
 }  // namespace
@@ -988,9 +1006,9 @@ hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds, 
 hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(kRecThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(kRecThreads), 0, s, a);
     return hipGetLastError();
 }
 

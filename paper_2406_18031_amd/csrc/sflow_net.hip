@@ -29,7 +29,7 @@ struct sf_net_s {
     uint16_t* wf = nullptr;         // BF16 [4][9][16][16]
     uint16_t* wb = nullptr;
     float* bias = nullptr;          // [4][16]
-    float* in = nullptr;            // [6][total]
+    float* in = nullptr;            // [kCnnInputs][total]
     float* tgt = nullptr;           // [3][total]
     float* out = nullptr;           // [3][total]
     uint16_t* act[4] = {};          // layer inputs, BF16 NHWC 16
@@ -38,6 +38,7 @@ struct sf_net_s {
     float* loss = nullptr;
     int64_t step = 0;
     bool has_params = false;
+    float eps = 1e-3f;              // Charbonnier epsilon of the loss, pixels
 };
 
 static std::string g_net_create_error;
@@ -79,7 +80,7 @@ static sf_status net_alive(sf_net n) {
 }
 
 static void layer_offsets(int woff[4], int boff[4], int cin[4], int cout[4]) {
-    static const int ch[5] = {6, 16, 16, 16, 3};
+    static const int ch[5] = {kCnnInputs, 16, 16, 16, 3};
     int off = 0;
     for (int l = 0; l < kCnnLayers; ++l) {
         cin[l] = ch[l];
@@ -105,7 +106,7 @@ static hipError_t repack(sf_net n) {
 // output planes in n->out
 static sf_status forward(sf_net n) {
     const int P = n->segs.total;
-    NET_TRY(n, launch_pack_inputs(n->in, 6, P, n->act[0], n->stream));
+    NET_TRY(n, launch_pack_inputs(n->in, kCnnInputs, P, n->act[0], n->stream));
     for (int l = 0; l < kCnnLayers; ++l) {
         ConvArgs a{};
         a.segs = n->segs;
@@ -164,7 +165,7 @@ sf_status sf_net_create(const int32_t* rows, const int32_t* cols, int32_t n_imag
         kCnnParams * 4, kCnnParams * 4, kCnnParams * 4, kCnnParams * 4,   // params m v grad
         4 * 9 * 256 * 4, 4 * 16 * 4,                                      // dw db
         4 * 9 * 256 * 2, 4 * 9 * 256 * 2, 4 * 16 * 4,                     // wf wb bias
-        6 * P * 4, 3 * P * 4, 3 * P * 4,                                  // in tgt out
+        kCnnInputs * P * 4, 3 * P * 4, 3 * P * 4,                         // in tgt out
         P * 32, P * 32, P * 32, P * 32, P * 32, P * 32, P * 32,           // act[4] g[2] dout
         256};                                                             // loss
     size_t total = 0;
@@ -241,7 +242,7 @@ sf_status sf_net_forward(sf_net n, const float* in, float* out) {
     if (st != SF_OK) return st;
     if (!n->has_params) return nfail(n, SF_ERR_STATE, "no parameters set");
     if (!dev_ptr(in) || !dev_ptr(out)) return nfail(n, SF_ERR_INVALID_ARG, "in and out must be device pointers");
-    NET_TRY(n, launch_planes_in(n->segs, in, 6, n->in, n->stream));
+    NET_TRY(n, launch_planes_in(n->segs, in, kCnnInputs, n->in, n->stream));
     st = forward(n);
     if (st != SF_OK) return st;
     NET_TRY(n, launch_planes_out(n->segs, n->out, 3, out, n->stream));
@@ -256,7 +257,7 @@ sf_status sf_net_train_step(sf_net n, const float* in, const float* target, floa
     if (!dev_ptr(in) || !dev_ptr(target))
         return nfail(n, SF_ERR_INVALID_ARG, "in and target must be device pointers");
     if (!(lr >= 0.0f) || !isfinite(lr)) return nfail(n, SF_ERR_INVALID_ARG, "lr must be finite and >= 0");
-    NET_TRY(n, launch_planes_in(n->segs, in, 6, n->in, n->stream));
+    NET_TRY(n, launch_planes_in(n->segs, in, kCnnInputs, n->in, n->stream));
     NET_TRY(n, launch_planes_in(n->segs, target, 3, n->tgt, n->stream));
     st = forward(n);
     if (st != SF_OK) return st;
@@ -267,7 +268,7 @@ sf_status sf_net_train_step(sf_net n, const float* in, const float* target, floa
     la.segs = n->segs;
     la.out = n->out;
     la.target = n->tgt;
-    la.eps = 1e-3f;
+    la.eps = n->eps;
     la.inv_count = (float)(1.0 / (double)n->pixels);
     la.loss = n->loss;
     la.dout = n->dout;
@@ -327,6 +328,14 @@ sf_status sf_net_train_step(sf_net n, const float* in, const float* target, floa
     if (grad_out)
         NET_TRY(n, hipMemcpyAsync(grad_out, n->grad, kCnnParams * 4, hipMemcpyDeviceToHost, n->stream));
     NET_TRY(n, hipStreamSynchronize(n->stream));
+    return SF_OK;
+}
+
+sf_status sf_net_set_loss(sf_net n, float eps) {
+    sf_status st = net_alive(n);
+    if (st != SF_OK) return st;
+    if (!(eps > 0.0f) || !isfinite(eps)) return nfail(n, SF_ERR_INVALID_ARG, "eps must be finite and > 0");
+    n->eps = eps;
     return SF_OK;
 }
 

@@ -3,9 +3,10 @@
 Everything numeric runs in the library (include/sflow.h, sections "learned update" and
 "training the learned update's network"): the filter writes each frame's network inputs,
 the network object runs forward, loss, backward and Adam on the matrix cores.  This module
-only arranges tensors.  The update replaces, at the finest level, the least-squares solution
-of the paper's update step (Section "State update") by the network's flow where the
-least-squares cost increase stays under a threshold.
+only arranges tensors.  At the finest level the network corrects the output flow of the
+paper's update step (Section "State update"), the smoothed least-squares solution, where the
+least-squares cost of the correction stays under a threshold; the filter's state and
+recurrence stay the plain ones.
 """
 from __future__ import annotations
 
@@ -15,7 +16,7 @@ import numpy as np
 
 from . import sflow
 
-CHANNELS = (6, 16, 16, 16, 3)
+CHANNELS = (9, 16, 16, 16, 3)
 N_PARAMS = sflow.SF_LEARNED_PARAMS
 
 
@@ -57,23 +58,24 @@ def join_params(layers) -> np.ndarray:
 
 
 def sample(update_inputs, w_frame):
-    """Network input (6, R, C) and target correction (3, R, C) of one frame.
+    """Network input (9, R, C) and target output (3, R, C) of one frame.
 
-    update_inputs: the 16 planes of sf_get_update_inputs; w_frame: the true structure flow
+    update_inputs: the 22 planes of sf_get_update_inputs; w_frame: the true structure flow
     of that frame in rad/frame, (3, R, C).  The target is the correction (pixels per frame)
-    that takes the predicted field to the true one: (w - parent - x0) / dmu."""
-    x0 = update_inputs[6:9]
-    parent = update_inputs[12:15]
-    dmu = update_inputs[15]
-    return update_inputs[0:6], (w_frame - parent - x0) / dmu
+    that takes the smoothed least-squares field to the true one: (w - parent - S(x_ls)) / dmu.
+    """
+    xs = update_inputs[15:18]
+    parent = update_inputs[18:21]
+    dmu = update_inputs[21]
+    return update_inputs[0:9], (w_frame - parent - xs) / dmu
 
 
 def train(sizes: Sequence[Tuple[int, int]], batches: Iterable, params: np.ndarray,
-          lr: float = 2e-3, stream=None, log_every: int = 0):
+          lr: float = 2e-3, stream=None, log_every: int = 0, loss_eps: float = 1e-3):
     """Adam over `batches`, an iterable of (inputs, targets) device tensors laid out as the
-    network object expects (images one after the other, inputs [6][R][C], targets [3][R][C]).
+    network object expects (images one after the other, inputs [9][R][C], targets [3][R][C]).
     Returns (parameters, losses)."""
-    net = sflow.Net(sizes, params, stream)
+    net = sflow.Net(sizes, params, stream, loss_eps)
     losses = []
     try:
         for k, (inp, tgt) in enumerate(batches):

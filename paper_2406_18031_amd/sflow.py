@@ -33,8 +33,8 @@ SF_MAX_LEVELS = 8
 FLOW_COMPONENTS = {SF_FLOW_W_RAD_S: 3, SF_FLOW_TANGENT_PX: 2, SF_FLOW_NORMAL_PX: 1,
                    SF_FLOW_RHO: 1, SF_FLOW_W_FRAME: 3}
 DEFAULT_ALPHA = (300.0, 1000.0, 1.0, 1.0, 1.0)
-SF_LEARNED_PARAMS = 5955
-SF_UPDATE_INPUT_PLANES = 16
+SF_LEARNED_PARAMS = 6387
+SF_UPDATE_INPUT_PLANES = 22
 
 
 class sf_config(ctypes.Structure):
@@ -59,6 +59,11 @@ class SflowError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2406_18031_amd.build")
+    # Load torch's HIP runtime first: the library's libamdhip64.so.7 dependency then binds to
+    # that same runtime instance, so torch's streams and allocations are valid in the library.
+    # Loaded the other way round, the process can end up with two HIP runtimes (torch asks for
+    # its bundled copy under another file name), which share no devices or streams.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, st = ctypes.c_void_p, ctypes.c_int
     sig = {
@@ -95,6 +100,7 @@ def _load():
         "sf_net_get_params": (st, [vp, vp, ctypes.c_size_t]),
         "sf_net_forward": (st, [vp, vp, vp]),
         "sf_net_train_step": (st, [vp, vp, vp, ctypes.c_float, vp, vp]),
+        "sf_net_set_loss": (st, [vp, ctypes.c_float]),
         "sf_net_destroy": (st, [vp]),
         "sf_net_last_error": (ctypes.c_char_p, [vp]),
     }
@@ -112,7 +118,8 @@ EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_st
             "sf_set_cameras", "sf_push_frames", "sf_get_flow_stream", "sf_state_size_stream",
             "sf_get_state_stream", "sf_set_state_stream", "sf_set_learned", "sf_learned_stats",
             "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
-            "sf_net_forward", "sf_net_train_step", "sf_net_destroy", "sf_net_last_error")
+            "sf_net_forward", "sf_net_train_step", "sf_net_set_loss", "sf_net_destroy",
+            "sf_net_last_error")
 
 
 def _check(status: int, ctx) -> None:
@@ -327,6 +334,10 @@ def sf_net_train_step(net: int, inp, target, lr: float, want_grad: bool = False)
     return float(loss[0]), grad
 
 
+def sf_net_set_loss(net: int, eps: float) -> None:
+    _net_check(lib.sf_net_set_loss(net, eps), net)
+
+
 def sf_net_destroy(net: int) -> None:
     _net_check(lib.sf_net_destroy(net), net)
 
@@ -438,10 +449,12 @@ class Filter:
 class Net:
     """Convenience wrapper owning one trainer network over a fixed list of image sizes."""
 
-    def __init__(self, sizes, params, stream=None):
+    def __init__(self, sizes, params, stream=None, loss_eps=None):
         self.sizes = [(int(r), int(c)) for r, c in sizes]
         self.net = sf_net_create(self.sizes, stream)
         sf_net_set_params(self.net, params)
+        if loss_eps is not None:
+            sf_net_set_loss(self.net, loss_eps)
 
     def forward(self, inp, out=None):
         import torch

@@ -56,7 +56,7 @@ def test_network_forward_matches_oracle():
     layers = _params(1)
     flat = _flat(layers)
     rl = [(bf16(W), b) for W, b in layers]          # the weights the matrix cores see
-    xs = _images(rng, 6)
+    xs = _images(rng, 9)
     net = sflow.Net(SIZES, flat)
     out = _split(net.forward(_cat(xs)).cpu().numpy().astype(np.float64), 3)
     num = den = 0.0
@@ -79,7 +79,7 @@ def test_network_gradients_match_oracle():
     layers = _params(2)
     flat = _flat(layers)
     rl = [(bf16(W), b) for W, b in layers]
-    xs = _images(rng, 6)
+    xs = _images(rng, 9)
     ts = _images(rng, 3)
     net = sflow.Net(SIZES, flat)
     loss, grad = net.train_step(_cat(xs), _cat(ts), 0.0, want_grad=True)
@@ -113,7 +113,7 @@ def test_training_reduces_loss():
     rng = np.random.default_rng(7)
     sizes = [(32, 32), (24, 40)]
     teacher = _params(3)
-    xs = _images(rng, 6, sizes)
+    xs = _images(rng, 9, sizes)
     ts = [cnn.forward(x.transpose(1, 2, 0), teacher)[0].transpose(2, 0, 1) for x in xs]
     params, losses = learned.train(sizes, [(_cat(xs), _cat(ts))] * 150,
                                    learned.init_params(4), lr=3e-3)
@@ -168,8 +168,8 @@ def test_negative_threshold_gives_the_plain_update(storage):
 
 
 def test_network_flow_and_smoothing_match_oracle():
-    """threshold = +inf: the flow is x0 + dmu * net(inputs), smoothed; checked against the
-    FP64 network oracle on the inputs the filter exported, and the oracle's smoothing."""
+    """threshold = +inf: the flow is S(x_ls) + dmu * net(inputs); checked against the FP64
+    network oracle on the inputs the filter exported and the oracle's smoothing."""
     from oracle import cnn
     from oracle.update import smooth
     from paper_2406_18031_amd import learned, sflow
@@ -185,16 +185,20 @@ def test_network_flow_and_smoothing_match_oracle():
         if k == 0:
             continue
         ui = lrn.update_inputs().cpu().numpy().astype(np.float64)
-        out, _, _ = cnn.forward(bf16(ui[0:6]).transpose(1, 2, 0), rl)
-        x = ui[6:9].transpose(1, 2, 0) + ui[15][..., None] * out
-        ref = smooth(x, 3)
+        dmu = ui[21][..., None]
+        out, _, _ = cnn.forward(bf16(ui[0:9]).transpose(1, 2, 0), rl)
+        xs = smooth(ui[12:15].transpose(1, 2, 0), 3)
+        np.testing.assert_allclose(ui[15:18].transpose(1, 2, 0), xs, rtol=1e-5,
+                                   atol=1e-6 * np.abs(xs).max())
+        ref = xs + dmu * out
         got = lrn.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy().transpose(1, 2, 0)
-        corr = smooth(ui[15][..., None] * out, 3)
-        err = np.linalg.norm(got - ref) / np.linalg.norm(corr)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(dmu * out)
         log(f"  frame {k}: rel err of the correction {err:.2e}")
         assert err <= 2e-2
-        # and the prior in the exported inputs is the scaled x0
-        np.testing.assert_allclose(ui[3:6] * 4.0 * ui[15], ui[6:9], rtol=1e-5, atol=1e-9)
+        # the exported inputs hold x0 and x_ls in pixels / 4; a top level has no parent
+        np.testing.assert_allclose(ui[3:6] * 4.0 * ui[21], ui[9:12], rtol=1e-5, atol=1e-9)
+        np.testing.assert_allclose(ui[6:9] * 4.0 * ui[21], ui[12:15], rtol=1e-5, atol=1e-9)
+        assert not ui[18:21].any()
     fb, px = lrn.learned_stats()
     assert fb == 0 and px == 2 * R * C
 

@@ -1,9 +1,9 @@
 """The learned update trained on the GPU beats the plain update on held-out sequences.
 
 Training data: the filter runs seeded box sequences (textured boxes and planes, constant
-linear velocity plus sinusoidal rotation, 1 % depth noise) with every pixel falling back, and
-exports each frame's network inputs; the targets are the corrections that reach the true
-structure flow.  Evaluation: other seeds, the plain and the learned filter side by side, the
+linear velocity plus sinusoidal rotation, 1 % depth noise) and exports each frame's network
+inputs; the targets are the corrections that reach the true structure flow.  The state does
+not depend on the network, so these are the inputs the trained network will see.  Evaluation: other seeds, the plain and the learned filter side by side, the
 endpoint error against the true flow in pixels per frame."""
 import numpy as np
 import pytest
@@ -41,12 +41,13 @@ def _frames(seq):
                (fr.w_gt * seq.dt).permute(2, 0, 1).to(torch.float32).contiguous())
 
 
-def _collect(seeds, params0):
+def _collect(seeds, params, threshold):
+    """Training pairs from the filter's own trajectories with the given parameters."""
     from paper_2406_18031_amd import learned, sflow
     data = []
     for s in seeds:
         seq = _seq(s)
-        f = _filter(seq, sflow.SF_UPDATE_LEARNED, params0, -1.0)
+        f = _filter(seq, sflow.SF_UPDATE_LEARNED, params, threshold)
         for k, Y, rho, w in _frames(seq):
             f.push(Y, rho, seq.dt)
             if k >= 1:
@@ -68,37 +69,30 @@ def _epe(f, seq, dmu):
     return float(np.mean(errs))
 
 
-def test_learned_update_beats_plain():
+def _train(data, params, steps, lr, seed):
     import torch
-    from paper_2406_18031_amd import learned, sflow
-    p0 = learned.init_params(0)
-    log("collecting training data")
-    data = _collect(TRAIN_SEEDS, p0)
-    log(f"  {len(data)} frames of {R}x{C}")
-    g = torch.Generator().manual_seed(0)
+    from paper_2406_18031_amd import learned
+    g = torch.Generator().manual_seed(seed)
 
-    def batches(n, bs=8):
-        for _ in range(n):
+    def batches(bs=8):
+        for _ in range(steps):
             idx = torch.randperm(len(data), generator=g)[:bs].tolist()
             yield (torch.cat([data[i][0].reshape(-1) for i in idx]),
                    torch.cat([data[i][1].reshape(-1) for i in idx]))
 
-    sizes = [(R, C)] * 8
-    params, losses = learned.train(sizes, batches(300), p0, lr=2e-3)
-    params, l2 = learned.train(sizes, batches(100), params, lr=5e-4)
-    losses += l2
-    log(f"  loss {np.mean(losses[:10]):.4f} -> {np.mean(losses[-10:]):.4f}")
-    assert np.mean(losses[-10:]) < np.mean(losses[:10])
+    return learned.train([(R, C)] * 8, batches(), params, lr=lr)
 
+
+def _evaluate(params, thresholds):
+    from paper_2406_18031_amd import sflow
     plain_e, learned_e, fb_rate = [], {}, {}
-    thresholds = (float("inf"), 1.0, 0.1)
     for s in EVAL_SEEDS:
         seq = _seq(s)
         probe = _filter(seq, sflow.SF_UPDATE_LEARNED, params, -1.0)
         k, Y, rho, w = next(_frames(seq))
         probe.push(Y, rho, seq.dt)
         probe.push(Y, rho, seq.dt)
-        dmu = probe.update_inputs()[15]
+        dmu = probe.update_inputs()[21]
         probe.close()
         plain_e.append(_epe(_filter(seq, sflow.SF_UPDATE_PLAIN), seq, dmu))
         for t in thresholds:
@@ -107,11 +101,26 @@ def test_learned_update_beats_plain():
             fb, px = f.learned_stats()
             fb_rate.setdefault(t, []).append(fb / px)
             f.close()
-    plain = float(np.mean(plain_e))
+    return (float(np.mean(plain_e)), {t: float(np.mean(v)) for t, v in learned_e.items()},
+            {t: float(np.mean(v)) for t, v in fb_rate.items()})
+
+
+def test_learned_update_beats_plain():
+    from paper_2406_18031_amd import learned
+    p0 = learned.init_params(0)
+    thresholds = (float("inf"), 1.0, 0.1)
+    log("collecting training data")
+    data = _collect(TRAIN_SEEDS, p0, -1.0)
+    log(f"  {len(data)} frames of {R}x{C}")
+    params, losses = _train(data, p0, 300, 2e-3, 0)
+    params, l2 = _train(data, params, 200, 5e-4, 1)
+    losses += l2
+    log(f"  loss {np.mean(losses[:10]):.4f} -> {np.mean(losses[-10:]):.4f}")
+    assert np.mean(losses[-10:]) < np.mean(losses[:10])
+    plain, lrn, fb = _evaluate(params, thresholds)
     log(f"  plain GT-EPE {plain:.4f} px/frame")
-    best = min(thresholds, key=lambda t: np.mean(learned_e[t]))
     for t in thresholds:
-        log(f"  learned threshold {t}: GT-EPE {np.mean(learned_e[t]):.4f}, "
-            f"fallback rate {np.mean(fb_rate[t]):.3f}")
-    assert np.mean(learned_e[best]) <= 1.05 * plain
-    assert np.mean(learned_e[best]) < plain
+        log(f"  learned threshold {t}: GT-EPE {lrn[t]:.4f}, fallback rate {fb[t]:.3f}")
+    best = min(thresholds, key=lambda t: lrn[t] if np.isfinite(lrn[t]) else np.inf)
+    assert lrn[best] <= 1.05 * plain
+    assert lrn[best] < plain

@@ -34,7 +34,7 @@ def test_gradients_match_finite_differences():
     # make the last layer as large as the others so that every gradient is exercised
     params[-1] = (params[-1][0] * 10.0, rng.standard_normal(3) * 0.1)
     params = [(W, b + 0.05 * rng.standard_normal(b.shape)) for W, b in params]
-    x = rng.standard_normal((6, 5, 6))
+    x = rng.standard_normal((6, 5, 9))
     target = rng.standard_normal((6, 5, 3))
 
     def loss(ps):
@@ -67,4 +67,4 @@ def test_gradients_match_finite_differences():
 
 def test_parameter_count():
     n = sum(W.size + b.size for W, b in cnn.init_params())
-    assert n == 5955
+    assert n == 6387
