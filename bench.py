@@ -110,8 +110,8 @@ def run_gpu(wl_name, steps, warmup, storage=0):
 
 def run_batched(n_streams, steps, warmup, storage=0, frames=6):
     """n_streams independent camera streams of mixed sizes advanced together: one pyramid
-    launch per depth, one level-step launch and one reconstruction launch per frame for all
-    streams.  A step is one frame of every stream plus every stream's output."""
+    launch per depth, one level-step launch and one reconstruction launch per depth per
+    frame for all streams.  A step is one frame of every stream plus every stream's output."""
     import torch
     from paper_2406_18031_amd import sflow
     from synth.workloads import stream_mix

@@ -157,7 +157,7 @@ const char* sf_last_error(sf_ctx ctx);
 /* ---- batches of camera streams -------------------------------------------------------------
  * A batch context advances up to 64 independent camera streams together: every frame runs one
  * pyramid launch per pyramid depth, one fused level-step launch over every tile of every level
- * of every stream, and one reconstruction launch for every lower level of every stream.  Streams
+ * of every stream, and one reconstruction launch per lower level, for all streams at once.  Streams
  * may differ in size, levels, maximum flow, smoothing, weights and readings, but not in
  * storage.  sf_create is sf_create_batch with n = 1; the single-stream calls (sf_set_camera,
  * sf_push_frame, sf_get_flow, sf_state_size, sf_get_state, sf_set_state) return

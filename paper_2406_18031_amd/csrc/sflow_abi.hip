@@ -6,7 +6,7 @@
 // 256 bytes, plus the entry table the kernels read.  A frame of every stream is: the pyramid
 // (one launch per pyramid depth, all streams together), one fused level-step launch covering
 // every tile of every level of every stream (levels are independent within a frame), then the
-// coarse-to-fine reconstruction of every lower level of every stream in one launch.  With the
+// coarse-to-fine reconstruction (one launch per depth, all streams together).  With the
 // learned update, the network and the choice kernel run between the step and the
 // reconstruction.
 #include <math.h>
@@ -650,7 +650,7 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         const double dp = c->st[s].dt_prev;
         in.scale[s] = (c->frames == 0 || dt[s] == dp) ? 1.0f : (float)(dt[s] / dp);
     }
-    // pyramid, finest to coarsest
+    // pyramid, finest to coarsest: one launch per depth for all streams
     for (int h = 1; h < c->max_levels; ++h) {
         ElemArgs a = elem_args(c, h, 0);
         a.in = in;
@@ -681,20 +681,19 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
             sf_status s2 = run_learned(c, q);
             if (s2 != SF_OK) return s2;
         }
-        {
-            // reconstruction of every level below the top, all streams, one launch
+        for (int h = c->max_levels - 2; h >= 0; --h) {
+            // reconstruction of level h for the streams where h is below the top
             ElemArgs r{};
             r.lv = c->lv_dev;
             r.parity = q;
             int b = 0;
             for (int s = 0; s < c->S; ++s) {
                 const StreamInfo& si = c->st[s];
-                if (si.H < 2) continue;
-                const LevelDev& L0 = c->lv[si.e0];
-                r.ent[r.n] = si.e0;
+                if (h >= si.H - 1) continue;
+                const int e = si.e0 + h;
+                r.ent[r.n] = e;
                 r.blk[r.n] = b;
-                b += ((L0.rows + kReconstructTile - 1) / kReconstructTile) *
-                     ((L0.cols + kReconstructTile - 1) / kReconstructTile);
+                b += (c->lv[e].rows * c->lv[e].cols + kElemBlock - 1) / kElemBlock;
                 ++r.n;
             }
             r.blk[r.n] = b;

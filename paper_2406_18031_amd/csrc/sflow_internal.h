@@ -89,9 +89,6 @@ hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds_bytes,
                        hipStream_t s);
-// reconstruction of every level below the top: entries are the streams' finest levels, blocks
-// are kReconstructTile^2 tiles of them
-constexpr int kReconstructTile = 32;
 hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_output(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_learned_extract(int storage, const ElemArgs& a, hipStream_t s);

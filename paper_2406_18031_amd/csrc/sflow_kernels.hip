@@ -575,10 +575,25 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup w runs on XCD w mod 8), and
+// each XCD has its own L2.  Hand out tiles in groups of G consecutive ones per XCD instead
+// (G = min(32, n / 8)), so that neighbouring tiles, which read overlapping halos, mostly share
+// an L2 while the XCDs still alternate over the grid; a bijection of [0, n), the identity on
+// the tail that does not fill a whole round of groups.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local_block(int w, int n) {
+    const int g = min(32, n / kXcds);
+    if (g == 0) return w;
+    const int full = n / (kXcds * g) * (kXcds * g);
+    if (w >= full) return w;
+    const int x = w % kXcds, k = w / kXcds;      // k-th workgroup dispatched to XCD x
+    return ((k / g) * kXcds + x) * g + k % g;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     extern __shared__ float lds[];
-    const int b = blockIdx.x;
+    const int b = xcd_local_block(blockIdx.x, gridDim.x);
     // the entry owning this block: the last one whose first block is <= b
     int lo = 0, hi = a.nent - 1;
     while (lo < hi) {
@@ -673,103 +688,29 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
     }
 }
 
-// Coarse-to-fine reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h of every level
-// below the top, in state[parity], in one launch.  A block owns a kRecTile x kRecTile tile of
-// the finest level; it computes, coarsest first, the patch of every lower level that the tile
-// depends on (each level's patch from the one above, held in LDS as the values the state
-// store will hold), and stores the level-h pixels whose finest-level image (2^h i, 2^h j)
-// lies in its tile, so every pixel is stored once and every block sees the same values.
-constexpr int kRecTile = kReconstructTile;
-constexpr int kRecPatch = kRecTile / 2 + 1;       // rows/cols of a patch at level >= 1
-
-template <typename T> __device__ __forceinline__ float stored(float v);
-template <> __device__ __forceinline__ float stored<float>(float v) { return v; }
-template <> __device__ __forceinline__ float stored<__half>(float v) {
-    return __half2float(__float2half(v));
-}
-
-constexpr int kRecThreads = kRecTile * kRecTile;   // one finest-level pixel per thread
-
+// reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[parity]
 template <typename T>
-__global__ void __launch_bounds__(kRecThreads) k_reconstruct(ElemArgs a) {
-    __shared__ float P[2][3][kRecPatch * kRecPatch];
-    const int b = blockIdx.x;
-    int k = 0;
-    while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
-    const int e0 = a.ent[k];
-    const LevelDev& L0 = a.lv[e0];
-    const int t = b - a.blk[k];
-    const int tiles_x = (L0.cols + kRecTile - 1) / kRecTile;
-    const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int ti0 = ty * kRecTile, tj0 = tx * kRecTile;
-    // patch bounds per level, finest first, up to the level below the top
-    int ra[kMaxLevels], rb[kMaxLevels], ca[kMaxLevels], cb[kMaxLevels];
-    int nl = 0;                                     // levels below the top
-    {
-        int e = e0;
-        ra[0] = ti0;
-        rb[0] = min(ti0 + kRecTile, L0.rows);
-        ca[0] = tj0;
-        cb[0] = min(tj0 + kRecTile, L0.cols);
-        while (!a.lv[e].top) {
-            const LevelDev& U = a.lv[a.lv[e].parent];
-            if (nl + 1 < kMaxLevels) {
-                ra[nl + 1] = ra[nl] >> 1;
-                rb[nl + 1] = min(((rb[nl] - 1) >> 1) + 2, U.rows);
-                ca[nl + 1] = ca[nl] >> 1;
-                cb[nl + 1] = min(((cb[nl] - 1) >> 1) + 2, U.cols);
-            }
-            e = a.lv[e].parent;
-            ++nl;
-        }
-    }
+__global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
+    int e, i, j;
+    if (!elem_pixel(a, e, i, j)) return;
+    const LevelDev& L = a.lv[e];
+    const LevelDev& U = a.lv[L.parent];
     const int q = a.parity;
-    for (int h = nl - 1; h >= 0; --h) {
-        const LevelDev& L = a.lv[e0 + h];
-        const LevelDev& U = a.lv[L.parent];
-        const bool parent_top = h == nl - 1;
-        const float uin = flow_in_scale<T>(U);
-        const float lin = flow_in_scale<T>(L);
-        const float lout = flow_out_scale<T>(L);
-        const int pw = cb[h + 1 < kMaxLevels ? h + 1 : h] - ca[h + 1 < kMaxLevels ? h + 1 : h];
-        const int pa = ra[h + 1 < kMaxLevels ? h + 1 : h], pc = ca[h + 1 < kMaxLevels ? h + 1 : h];
-        const float* src = P[(h + 1) & 1][0];
-        float* dst = P[h & 1][0];
-        const int w = cb[h] - ca[h];
-        const int n = (rb[h] - ra[h]) * w;
-        for (int p = threadIdx.x; p < n; p += kRecThreads) {
-            const int i = ra[h] + p / w;
-            const int j = ca[h] + p % w;
-            const int i0 = i >> 1, j0 = j >> 1;
-            const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
-            const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
-            const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
-            const float w10 = fi * (1.0f - fj), w11 = fi * fj;
-            const size_t go = (size_t)i * L.pitch + j;
-            const bool own = h == 0 || (((i << h) >= ti0) && ((i << h) < ti0 + kRecTile) &&
-                                        ((j << h) >= tj0) && ((j << h) < tj0 + kRecTile));
-            for (int c = 0; c < 3; ++c) {
-                float p00, p01, p10, p11;
-                if (parent_top) {
-                    const T* W = (const T*)U.w[q][c];
-                    p00 = ldv(W, (size_t)i0 * U.pitch + j0);
-                    p01 = ldv(W, (size_t)i0 * U.pitch + j1);
-                    p10 = ldv(W, (size_t)i1 * U.pitch + j0);
-                    p11 = ldv(W, (size_t)i1 * U.pitch + j1);
-                } else {
-                    const float* S = src + c * kRecPatch * kRecPatch;
-                    p00 = S[(i0 - pa) * pw + (j0 - pc)];
-                    p01 = S[(i0 - pa) * pw + (j1 - pc)];
-                    p10 = S[(i1 - pa) * pw + (j0 - pc)];
-                    p11 = S[(i1 - pa) * pw + (j1 - pc)];
-                }
-                const float cc = w00 * p00 + w01 * p01 + w10 * p10 + w11 * p11;
-                const float v = cc * uin + ldv((const T*)L.dw[q][c], go) * lin;
-                if (own) stv((T*)L.w[q][c], go, v * lout);
-                if (h > 0) dst[c * kRecPatch * kRecPatch + p] = stored<T>(v * lout);
-            }
-        }
-        __syncthreads();
+    const int i0 = i >> 1, j0 = j >> 1;
+    const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
+    const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
+    const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
+    const float w10 = fi * (1.0f - fj), w11 = fi * fj;
+    const float uin = flow_in_scale<T>(U);
+    const float lin = flow_in_scale<T>(L);
+    const float lout = flow_out_scale<T>(L);
+    const size_t go = (size_t)i * L.pitch + j;
+    for (int k = 0; k < 3; ++k) {
+        const T* W = (const T*)U.w[q][k];
+        const float c = w00 * ldv(W, (size_t)i0 * U.pitch + j0) + w01 * ldv(W, (size_t)i0 * U.pitch + j1) +
+                        w10 * ldv(W, (size_t)i1 * U.pitch + j0) + w11 * ldv(W, (size_t)i1 * U.pitch + j1);
+        const float v = c * uin + ldv((const T*)L.dw[q][k], go) * lin;
+        stv((T*)L.w[q][k], go, v * lout);
     }
 }
 
@@ -1006,9 +947,9 @@ hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds, 
 hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(kRecThreads), 0, s, a);
+        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(kRecThreads), 0, s, a);
+        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
     return hipGetLastError();
 }
 

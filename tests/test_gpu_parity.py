@@ -73,6 +73,17 @@ def test_ragged_multi_tile(flags):
     log("ragged flags", flags, "worst mean EPE", w)
 
 
+def test_deep_pyramid():
+    """Six levels: the first four pyramid levels come from the fused launch, the deeper ones
+    from one launch per level; reconstruction through all of them."""
+    rng = np.random.default_rng(17)
+    R, C = 150, 131
+    frames = _random_frames(rng, R, C, 4)
+    w = _run(frames, R, C, 6, 8.0, [2, 2, 2, 2, 1, 1], (120.0, 110.0, 64.2, 73.9),
+             dts=[0.01] * 4)
+    log("six levels worst mean EPE", w)
+
+
 def test_plane64_sequence():
     """The 64x64 one-level sinusoid-plane workload, all 20 frames."""
     from synth.workloads import workload
