@@ -177,9 +177,20 @@ sf_status sf_set_state_stream(sf_ctx ctx, int32_t stream, const void* host_blob,
 
 /* Tile shape of the fused level kernel for level h (1-based, all streams that have it):
  * output tiles of tw x th pixels; tw + 2*halo_h and th + 2*halo_h must not exceed 64, where
- * halo_h = max(N_h, 2) + 2 * smooth_iters[h-1].  0, 0 restores the built-in choice.  For
- * tuning. */
+ * halo_h = max(n, 2) + 2 * smooth_iters[h-1] with n the steps of the level's last prediction
+ * pass (N_h unless split, see sf_set_pass_steps; earlier passes use the built-in choice when
+ * the shape does not fit them).  0, 0 restores the built-in choice.  For tuning. */
 sf_status sf_set_tile(sf_ctx ctx, int32_t level, int32_t tw, int32_t th);
+
+/* Prediction steps per level-step launch (default 8).  A level whose prediction takes more
+ * steps N (N_h of Section "Numerical prediction") runs it in ceil(N / steps) launches, each
+ * over tiles with a halo of only its own steps, handing the transported fields on in FP32
+ * device buffers (allocated here; set-up work).  The result is bitwise the same for any value;
+ * smaller values trade an extra launch for less redundant halo work, which pays when many
+ * tiles are in flight (batches, large images, large flows).  Also lifts the limit on the
+ * maximum flow: only the last pass's halo, max(steps, 2) + 2*smooth, must fit the region.
+ * SF_ERR_UNSUPPORTED if some level's last pass would not fit. */
+sf_status sf_set_pass_steps(sf_ctx ctx, int32_t steps);
 
 /* Kernel timing for measurement.  When enabled, every push records HIP events around each
  * kernel on the context stream; sf_kernel_times returns, per kernel kind (0 pyramid,

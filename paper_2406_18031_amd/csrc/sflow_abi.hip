@@ -49,7 +49,15 @@ struct sf_ctx_s {
     LevelDev* lv_dev = nullptr;
     int user_tw[kMaxLevels]{};
     int user_th[kMaxLevels]{};
-    int nblocks = 0;
+    // step launches: the prediction of a level with N > pass_steps is split into passes
+    int pass_steps = kDefaultPassSteps;
+    struct StepLaunch { int e0, n, nblocks; };
+    std::vector<LevelDev> sv;       // pass entries, launch by launch
+    std::vector<StepLaunch> step_launches;
+    LevelDev* sv_dev = nullptr;
+    size_t sv_cap = 0;              // entries sv_dev can hold
+    float* mid = nullptr;           // FP32 fields between passes (two sets per split level)
+    size_t mid_bytes = 0;
     size_t lds_bytes = 0;
     int max_levels = 0;
     // timing
@@ -98,6 +106,19 @@ static sf_status hip_fail(sf_ctx c, hipError_t e, const char* what) {
     } while (0)
 
 static int level_halo(int N, int Ns) { return std::max(N, 2) + 2 * Ns; }
+
+// A prediction of N steps split into passes of at most ps steps: the number of passes and the
+// steps of pass i (equal shares, the last one taking the rest).
+static int npasses(int N, int ps) { return (N + ps - 1) / ps; }
+static int pass_len(int N, int P, int i) {
+    const int q = (N + P - 1) / P;
+    return i < P - 1 ? q : N - (P - 1) * q;
+}
+// halo of the last pass, the largest of the level's passes
+static int last_pass_halo(int N, int Ns, int ps) {
+    const int P = npasses(N, ps);
+    return level_halo(pass_len(N, P, P - 1), Ns);
+}
 
 static int level_steps(float max_flow, int h) {   // h is 0-based
     double v = ceil((double)max_flow / ldexp(1.0, h));
@@ -161,7 +182,8 @@ static sf_status validate_config(const sf_config* cfg, sf_config* out) {
                                     SF_READ_NO_CFL_CLAMP))
         return fail(nullptr, SF_ERR_INVALID_ARG, "unknown read_flags bits");
     for (int h = 0; h < c.levels; ++h) {
-        int halo = level_halo(level_steps(c.max_flow_px, h), c.smooth_iters[h]);
+        int halo = last_pass_halo(level_steps(c.max_flow_px, h), c.smooth_iters[h],
+                                  kDefaultPassSteps);
         if (2 * halo >= kRegion)
             return fail(nullptr, SF_ERR_UNSUPPORTED,
                         "level %d needs a halo of %d pixels (max(N,2) + 2*smooth); at most %d fit",
@@ -187,15 +209,63 @@ static void choose_tiles(sf_ctx c, LevelDev& L) {
     L.tiles_y = (L.rows + th - 1) / th;
 }
 
-static void layout_blocks(sf_ctx c) {
-    int b = 0;
-    for (auto& L : c->lv) {
-        choose_tiles(c, L);
-        L.block0 = b;
-        b += L.tiles_x * L.tiles_y;
+// Pass entries and step launches.  A level with P passes runs pass i in launch
+// Pmax - P + i, so every level's last pass (update, smoothing, store) is in the last launch.
+// Returns the bytes of FP32 intermediate fields the split levels need.
+static size_t layout_blocks(sf_ctx c) {
+    int pmax = 1;
+    for (auto& L : c->lv) pmax = std::max(pmax, npasses(L.N, c->pass_steps));
+    c->sv.clear();
+    c->step_launches.clear();
+    size_t mid_off = 0;
+    std::vector<size_t> mid_at(c->lv.size(), 0);
+    for (size_t e = 0; e < c->lv.size(); ++e) {
+        const LevelDev& L = c->lv[e];
+        if (npasses(L.N, c->pass_steps) > 1) {
+            mid_at[e] = mid_off;
+            mid_off += 2 * 8 * ((size_t)L.rows * L.pitch * sizeof(float) + 255) / 256 * 256;
+        }
     }
-    c->nblocks = b;
+    for (int k = 0; k < pmax; ++k) {
+        sf_ctx_s::StepLaunch sl{(int)c->sv.size(), 0, 0};
+        int b = 0;
+        for (size_t e = 0; e < c->lv.size(); ++e) {
+            LevelDev& L = c->lv[e];
+            const int P = npasses(L.N, c->pass_steps);
+            const int i = k - (pmax - P);
+            if (i < 0) continue;
+            LevelDev S = L;
+            S.pass_n = pass_len(L.N, P, i);
+            S.pass_first = i == 0;
+            S.pass_last = i == P - 1;
+            S.halo = S.pass_last ? level_halo(S.pass_n, L.Ns) : S.pass_n;
+            const size_t plane = ((size_t)L.rows * L.pitch * sizeof(float) + 255) / 256 * 256;
+            for (int f = 0; f < 8; ++f) {
+                S.mid_in[f] = nullptr;
+                S.mid_out[f] = nullptr;
+                if (P > 1 && c->mid) {
+                    float* base = (float*)((char*)c->mid + mid_at[e]);
+                    if (!S.pass_first)
+                        S.mid_in[f] = (float*)((char*)base + (((i - 1) & 1) * 8 + f) * plane);
+                    if (!S.pass_last)
+                        S.mid_out[f] = (float*)((char*)base + ((i & 1) * 8 + f) * plane);
+                }
+            }
+            choose_tiles(c, S);
+            S.block0 = b;
+            b += S.tiles_x * S.tiles_y;
+            if (S.pass_last) {   // the level's own entry keeps the tiles of its last pass
+                L.tw = S.tw; L.th = S.th; L.tiles_x = S.tiles_x; L.tiles_y = S.tiles_y;
+                L.halo = S.halo;
+            }
+            c->sv.push_back(S);
+            ++sl.n;
+        }
+        sl.nblocks = b;
+        c->step_launches.push_back(sl);
+    }
     c->lds_bytes = kLdsBytes;
+    return mid_off;
 }
 
 // per-pixel launch over the entries of level `level` (all streams that have it)
@@ -375,9 +445,43 @@ sf_status sf_stream_count(sf_ctx c, int32_t* n) {
 }
 
 static sf_status upload_levels(sf_ctx c) {
-    layout_blocks(c);
+    const size_t need = layout_blocks(c);
+    if (need > c->mid_bytes || c->sv.size() > c->sv_cap) {
+        // (re)allocate the intermediate fields and the pass table, then lay out again with the
+        // new addresses; this is set-up work (camera, tiles, pass length), not per frame
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (need > c->mid_bytes) {
+            if (c->mid) HIP_TRY(c, hipFree(c->mid));
+            c->mid = nullptr;
+            c->mid_bytes = 0;
+            hipError_t e = hipMalloc((void**)&c->mid, need);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                c->mid = nullptr;
+                return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                            "hipMalloc of %zu bytes for split predictions failed", need);
+            }
+            c->mid_bytes = need;
+        }
+        if (c->sv.size() > c->sv_cap) {
+            if (c->sv_dev) HIP_TRY(c, hipFree(c->sv_dev));
+            c->sv_dev = nullptr;
+            c->sv_cap = 0;
+            hipError_t e = hipMalloc((void**)&c->sv_dev, sizeof(LevelDev) * c->sv.size());
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                c->sv_dev = nullptr;
+                return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                            "hipMalloc of the pass table failed");
+            }
+            c->sv_cap = c->sv.size();
+        }
+        layout_blocks(c);
+    }
     HIP_TRY(c, prepare_kernels(c->lds_bytes));
     HIP_TRY(c, hipMemcpyAsync(c->lv_dev, c->lv.data(), sizeof(LevelDev) * c->lv.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->sv_dev, c->sv.data(), sizeof(LevelDev) * c->sv.size(),
                               hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SF_OK;
@@ -409,6 +513,8 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
             L.cyn = (float)(cy / fy);
             L.fx = (float)fx;
             L.N = level_steps(cf.max_flow_px, h);
+            L.pass_n = L.N;
+            L.pass_first = L.pass_last = 1;
             L.Ns = cf.smooth_iters[h];
             L.halo = level_halo(L.N, L.Ns);
             const double dmu0 = 1.0 / sqrt(fx * fx + 1.0);
@@ -445,7 +551,8 @@ sf_status sf_set_tile(sf_ctx c, int32_t level, int32_t tw, int32_t th) {
         for (int s = 0; s < c->S; ++s) {
             const StreamInfo& si = c->st[s];
             if (h >= si.H) continue;
-            const int halo = level_halo(level_steps(si.cfg.max_flow_px, h), si.cfg.smooth_iters[h]);
+            const int halo = last_pass_halo(level_steps(si.cfg.max_flow_px, h),
+                                            si.cfg.smooth_iters[h], c->pass_steps);
             if (tw < 1 || th < 1 || tw + 2 * halo > kRegion || th + 2 * halo > kRegion)
                 return fail(c, SF_ERR_INVALID_ARG, "tile %dx%d with halo %d exceeds %d", tw, th,
                             halo, kRegion);
@@ -454,6 +561,32 @@ sf_status sf_set_tile(sf_ctx c, int32_t level, int32_t tw, int32_t th) {
     c->user_tw[h] = tw;
     c->user_th[h] = th;
     if (c->camera) return upload_levels(c);
+    return SF_OK;
+}
+
+sf_status sf_set_pass_steps(sf_ctx c, int32_t steps) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (steps < 1 || steps > 64) return fail(c, SF_ERR_INVALID_ARG, "steps must be in [1, 64]");
+    for (int s = 0; s < c->S; ++s) {
+        const StreamInfo& si = c->st[s];
+        for (int h = 0; h < si.H; ++h) {
+            const int halo = last_pass_halo(level_steps(si.cfg.max_flow_px, h),
+                                            si.cfg.smooth_iters[h], steps);
+            if (2 * halo >= kRegion)
+                return fail(c, SF_ERR_UNSUPPORTED, "stream %d level %d: halo %d with %d steps per "
+                            "pass exceeds the region", s, h + 1, halo, steps);
+        }
+    }
+    const int old = c->pass_steps;
+    c->pass_steps = steps;
+    if (c->camera) {
+        sf_status s2 = upload_levels(c);
+        if (s2 != SF_OK) {
+            c->pass_steps = old;
+            return s2;
+        }
+    }
     return SF_OK;
 }
 
@@ -666,14 +799,14 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         }
         c->parity = 0;
     } else {
-        StepArgs a{};
-        a.lv = c->lv_dev;
-        a.nent = (int)c->lv.size();
-        a.parity = c->parity;
-        a.in = in;
-        {
+        for (const auto& sl : c->step_launches) {
+            StepArgs a{};
+            a.lv = c->sv_dev + sl.e0;
+            a.nent = sl.n;
+            a.parity = c->parity;
+            a.in = in;
             TimedLaunch t(c, 1);
-            HIP_TRY(c, launch_step(c->storage, a, c->nblocks, c->lds_bytes, c->stream));
+            HIP_TRY(c, launch_step(c->storage, a, sl.nblocks, c->lds_bytes, c->stream));
             t.done();
         }
         const int q = 1 - c->parity;
@@ -965,6 +1098,8 @@ sf_status sf_destroy(sf_ctx c) {
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->arena) (void)hipFree(c->arena);
     if (c->lbuf) (void)hipFree(c->lbuf);
+    if (c->mid) (void)hipFree(c->mid);
+    if (c->sv_dev) (void)hipFree(c->sv_dev);
     delete c;
     return SF_OK;
 }

@@ -18,7 +18,8 @@ constexpr size_t kLdsXB = 2 * (kBlock / 64) * 2 * 8 * 64 * sizeof(float);
 constexpr size_t kLdsPlanes = 5 * kRegion * 64 * sizeof(float);
 constexpr size_t kLdsBytes = kLdsXB > kLdsPlanes ? kLdsXB : kLdsPlanes;
 
-constexpr int kMaxStreams = 64;      // camera streams per context
+constexpr int kMaxStreams = 64;
+constexpr int kDefaultPassSteps = 8;   // prediction steps per step launch before a level splits      // camera streams per context
 // Planes of the learned-update buffers of a finest level: network inputs (6), prior x0 (3),
 // least-squares solution (3), cost terms a_Y (3), a_rho (3), G1, G2 (2) and the network's
 // output (3), each `ltotal` floats.
@@ -53,6 +54,14 @@ struct LevelDev {
     void* Y[2];
     void* Ym;                        // pyramid image of this frame (levels >= 1)
     void* Rm;                        // pyramid inverse depth of this frame (levels >= 1)
+    // The prediction of a level may be split over several step launches ("passes") of at most
+    // a few steps each, so that each pass needs a smaller halo.  A pass entry is a copy of its
+    // level's entry with its own halo and tiles, and:
+    int pass_n;                      // steps of this pass (N, the level's steps, sets dt)
+    int pass_first;                  // 1: loads the frame-k state (and applies the dt rescale)
+    int pass_last;                   // 1: runs the update, smoothing and state store
+    float* mid_in[8];                // FP32 fields after the previous pass (pitch = pitch)
+    float* mid_out[8];               // FP32 fields after this pass
 };
 
 // Per-frame arguments: the finest-level measurements of every stream (caller's device
@@ -64,7 +73,7 @@ struct FrameInputs {
 };
 
 struct StepArgs {
-    const LevelDev* lv;
+    const LevelDev* lv;              // the pass entries of this launch
     int nent;                        // entries; entry e owns blocks [lv[e].block0, lv[e+1].block0)
     int parity;                      // state[parity] is frame k, state[1 - parity] receives k+1
     FrameInputs in;

@@ -253,7 +253,16 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
 
     // ---- load the frame-k state of the region into registers ------------------------------
     float F[RPW][NF];
-    {
+    if (!L.pass_first) {    // a later pass of a split prediction: the fields after the last one
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            const bool ok = lane_ok && i >= vi0 && i < vi1;
+            const size_t g = (size_t)(ok ? i : 0) * L.pitch + (ok ? j : 0);
+#pragma unroll
+            for (int k = 0; k < NF; ++k) F[r][k] = ok ? L.mid_in[k][g] : 0.0f;
+        }
+    } else {
         const float fs = flow_in_scale<T>(L) * a.in.scale[L.stream];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
@@ -275,8 +284,27 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
         }
     }
 
+    // ---- measurements of the update, loaded now so that their latency hides behind the
+    // prediction: the new image at this wave's rows, the inverse depth at its rows and the rows
+    // just above and below (clamped to the image) ---------------------------------------------
+    const T* Ymeas = (const T*)(h == 0 ? a.in.Y[L.stream] : L.Ym);
+    const T* Rmeas = (const T*)(h == 0 ? a.in.R[L.stream] : L.Rm);
+    const int mp = h == 0 ? C : L.pitch;
+    float ypre[RPW], rpre[RPW + 2];
+    const bool meas = lane_ok && L.pass_last;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int i = wi0 + r;
+        ypre[r] = (meas && i >= 0 && i < R) ? ldv(Ymeas, (size_t)i * mp + j) : 0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < RPW + 2; ++t) {
+        const int i = clampi(wi0 - 1 + t, 0, R - 1);
+        rpre[t] = meas ? ldv(Rmeas, (size_t)i * mp + j) : 0.0f;
+    }
+
     // ---- prediction -------------------------------------------------------------------------
-    const int N = L.N;
+    const int N = L.N;                 // the level's steps: time step 1/N, stability bound N
     const float dt = 1.0f / (float)N;
     const float fN = (float)N;
     const float sig = (L.flags & SF_READ_SOURCE_LITERAL) ? 1.0f : 0.5f;
@@ -286,7 +314,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     int ci0 = vi0, ci1 = vi1, cj0 = vj0, cj1 = vj1;
     float* XB = lds;   // [2][NW][2][NF][64] boundary rows of every wave, double-buffered
 
-    for (int n = 0; n < N; ++n) {
+    for (int n = 0; n < L.pass_n; ++n) {   // the steps of this pass
         // column half-step: neighbours from adjacent lanes
         if (border)
             column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, wi0, ci0, ci1, at_left, at_right,
@@ -361,26 +389,34 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     }
     __syncthreads();   // the LDS below is reused for the update phase
 
+    if (!L.pass_last) {   // an earlier pass of a split prediction: hand the fields on
+        const bool tcol = j >= tj0 && j < tj1 && lane < RW;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            if (i < ti0 || i >= ti1 || !tcol) continue;
+            const size_t g = (size_t)i * L.pitch + j;
+#pragma unroll
+            for (int k = 0; k < NF; ++k) L.mid_out[k][g] = F[r][k];
+        }
+        return;
+    }
+
     // ---- update -------------------------------------------------------------------------------
     const int Ns = L.Ns;
     const int si0 = max(ti0 - 2 * Ns, 0), si1 = min(ti1 + 2 * Ns, R);
     const int sj0 = max(tj0 - 2 * Ns, 0), sj1 = min(tj1 + 2 * Ns, C);
     const int mi0 = max(si0 - 2, 0), mi1 = min(si1 + 2, R);
-    const int mj0 = max(sj0 - 2, 0), mj1 = min(sj1 + 2, C);
     float* PHG = lds;                    // [64 rows][64 lanes]
     float* PHD = lds + kRegion * 64;
     float* PT = lds + 2 * kRegion * 64;  // [3][64][64] smoothing
-    const T* Ymeas = (const T*)(h == 0 ? a.in.Y[L.stream] : L.Ym);
-    const T* Rmeas = (const T*)(h == 0 ? a.in.R[L.stream] : L.Rm);
-    const int mp = h == 0 ? C : L.pitch;
-    const bool mcol = lane < RW && j >= mj0 && j < mj1;
 
     // horizontal taps of the image model in registers
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
         const int i = wi0 + r;
         if (i < mi0 || i >= mi1) continue;           // wave-uniform
-        const float y = mcol ? ldv(Ymeas, (size_t)i * mp + j) : 0.0f;
+        const float y = ypre[r];
         const float ym1 = clamp_prev(y, left_b);
         const float ym2 = clamp_prev(ym1, left_b);
         const float yp1 = clamp_next(y, right_b);
@@ -400,6 +436,14 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
         PHD[row * 64 + lane] = hd;
     }
     __syncthreads();
+
+    // column neighbours of the inverse depth (clamped at the image's left/right border)
+    float rleft[RPW], rright[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        rleft[r] = clamp_prev(rpre[r + 1], left_b);
+        rright[r] = clamp_next(rpre[r + 1], right_b);
+    }
 
     // vertical taps, depth model and the least-squares solve, per pixel
     {
@@ -424,15 +468,12 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 d1 = fmaf(gtap(aa), hd, d1);
                 d2 = fmaf(gtap(aa) * (float)aa, hg, d2);
             }
-            const size_t gm = (size_t)i * mp;
-            const float rc = ldv(Rmeas, gm + j);
+            const float rc = rpre[r + 1];
             const bool rv = !isnan(rc);
             float r1 = 0.0f, r2 = 0.0f;
             if (rv) {
-                r1 = minabs_diff(rc, ldv(Rmeas, gm + min(j + 1, C - 1)),
-                                 ldv(Rmeas, gm + max(j - 1, 0)));
-                r2 = minabs_diff(rc, ldv(Rmeas, (size_t)min(i + 1, R - 1) * mp + j),
-                                 ldv(Rmeas, (size_t)max(i - 1, 0) * mp + j));
+                r1 = minabs_diff(rc, rright[r], rleft[r]);
+                r2 = minabs_diff(rc, rpre[r + 2], rpre[r]);
             }
             // tangent basis and spacing at (i, j)
             const float rinv = grinv[r];

@@ -78,6 +78,7 @@ def _load():
         "sf_last_error": (ctypes.c_char_p, [vp]),
         "sf_set_tile": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "sf_set_timing": (st, [vp, ctypes.c_int32]),
+        "sf_set_pass_steps": (st, [vp, ctypes.c_int32]),
         "sf_kernel_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
         "sf_create_batch": (st, [ctypes.POINTER(sf_config), ctypes.c_int32, vp,
@@ -114,7 +115,7 @@ def _load():
 lib = _load()
 EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_state_size",
             "sf_get_state", "sf_set_state", "sf_destroy", "sf_last_error", "sf_set_tile",
-            "sf_set_timing", "sf_kernel_times", "sf_create_batch", "sf_stream_count",
+            "sf_set_timing", "sf_kernel_times", "sf_set_pass_steps", "sf_create_batch", "sf_stream_count",
             "sf_set_cameras", "sf_push_frames", "sf_get_flow_stream", "sf_state_size_stream",
             "sf_get_state_stream", "sf_set_state_stream", "sf_set_learned", "sf_learned_stats",
             "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
@@ -209,6 +210,10 @@ def sf_last_error(ctx: Optional[int]) -> str:
 
 def sf_set_tile(ctx: int, level: int, tw: int, th: int) -> None:
     _check(lib.sf_set_tile(ctx, level, tw, th), ctx)
+
+
+def sf_set_pass_steps(ctx: int, steps: int) -> None:
+    _check(lib.sf_set_pass_steps(ctx, steps), ctx)
 
 
 def sf_set_timing(ctx: int, enable: bool) -> None:

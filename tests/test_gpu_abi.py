@@ -41,8 +41,9 @@ def test_config_validation(sf):
     ]
     for cfg in bad:
         assert _code(sf.sf_create, cfg, 0) == sf.SF_ERR_INVALID_ARG, sf.sf_last_error(None)
-    # halo larger than the 64-pixel region; the learned update with more than 4 smoothing passes
-    assert _code(sf.sf_create, sf.make_config(256, 256, 1, 30.0, [2]), 0) == sf.SF_ERR_UNSUPPORTED
+    # halo larger than the 64-pixel region even with the prediction split (16 smoothing passes);
+    # the learned update with more than 4 smoothing passes
+    assert _code(sf.sf_create, sf.make_config(256, 256, 1, 4.0, [16]), 0) == sf.SF_ERR_UNSUPPORTED
     assert _code(sf.sf_create, sf.make_config(64, 64, 1, 1.0, [5], update=1), 0) == \
         sf.SF_ERR_UNSUPPORTED
     assert _code(sf.sf_create, sf.make_config(64, 64, 1, 1.0, [2], update=2), 0) == \
@@ -79,6 +80,14 @@ def test_call_errors_and_state_rules(sf):
     buf = ctypes.create_string_buffer(n - 4)
     assert sf.lib.sf_get_state(ctx, buf, n - 4) == sf.SF_ERR_INVALID_ARG
     assert sf.lib.sf_set_tile(ctx, 1, 60, 60) == sf.SF_ERR_INVALID_ARG
+    assert sf.lib.sf_set_pass_steps(ctx, 0) == sf.SF_ERR_INVALID_ARG
+    assert sf.lib.sf_set_pass_steps(ctx, 65) == sf.SF_ERR_INVALID_ARG
+    assert sf.lib.sf_set_pass_steps(ctx, 1) == sf.SF_OK
+    sf.sf_destroy(ctx)
+    # a halo that fits only when the prediction is split: 30 steps with 4 smoothing passes
+    big = sf.make_config(64, 64, 1, 30.0, [4])
+    ctx = sf.sf_create(big)
+    assert sf.lib.sf_set_pass_steps(ctx, 32) == sf.SF_ERR_UNSUPPORTED
     sf.sf_destroy(ctx)
     assert sf.lib.sf_destroy(None) == sf.SF_OK
     assert sf.lib.sf_push_frame(None, None, None, 1.0) == sf.SF_ERR_INVALID_ARG

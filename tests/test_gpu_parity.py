@@ -84,6 +84,41 @@ def test_deep_pyramid():
     log("six levels worst mean EPE", w)
 
 
+@pytest.mark.parametrize("storage", [0, 1])
+def test_split_prediction_is_bitwise_identical(storage):
+    """Splitting a level's prediction over several launches (each over tiles with a smaller
+    halo, fields handed on in FP32) computes the same per-pixel arithmetic: bitwise equal."""
+    from paper_2406_18031_amd import sflow
+    rng = np.random.default_rng(23)
+    R, C = 100, 90
+    frames = _random_frames(rng, R, C, 4)
+    dtype = "float16" if storage == 1 else "float32"
+    outs = {}
+    for ps in (64, 5, 4, 1):
+        log(f"  pass steps {ps}, storage {storage}")
+        f = sflow.Filter(R, C, 2, 12.0, [2, 2], 90.0, 90.0, 44.5, 49.5, storage=storage)
+        sflow.sf_set_pass_steps(f.ctx, ps)
+        res = []
+        for k, (Y, rho) in enumerate(frames):
+            f.push(to_dev(Y, dtype), to_dev(rho, dtype), 0.01 if k < 2 else 0.02)
+            res.append(f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy())
+        outs[ps] = res
+        f.close()
+    for ps in (5, 4, 1):
+        for k in range(len(frames)):
+            assert np.array_equal(outs[ps][k], outs[64][k]), (ps, k)
+
+
+def test_large_flow_split_matches_oracle():
+    """A maximum flow whose single-launch halo would not fit the region (N = 28 at the finest
+    level) runs as four passes; parity with the oracle."""
+    rng = np.random.default_rng(29)
+    R, C = 96, 80
+    frames = _random_frames(rng, R, C, 4)
+    w = _run(frames, R, C, 2, 28.0, [2, 2], (80.0, 80.0, 39.5, 47.5), dts=[0.01] * 4)
+    log("max flow 28 worst mean EPE", w)
+
+
 def test_plane64_sequence():
     """The 64x64 one-level sinusoid-plane workload, all 20 frames."""
     from synth.workloads import workload
