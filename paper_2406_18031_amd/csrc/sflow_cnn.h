@@ -32,6 +32,7 @@ struct ConvArgs {
     int nout;                // meaningful output channels
     uint16_t* out;           // BF16 NHWC 16 channels (when not out_f32)
     float* out_f32;          // FP32 planes [nout][total] (when out_f32)
+    int tblk[kCnnMaxSegs + 1];   // first block of each image's 16 x 16 tiles (set by launch_conv)
 };
 
 struct DwArgs {

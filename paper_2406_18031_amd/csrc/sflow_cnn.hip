@@ -6,8 +6,9 @@
 // for a list of images stored one after the other ("segments"), each image's pixel range
 // padded to a multiple of 16 so that a wave's 16 pixels never straddle two images.
 //
-// Convolution as an implicit GEMM: a wave computes a 16-pixel x 16-output-channel tile with
-// nine v_mfma_f32_16x16x16_bf16 (one per tap, K = 16 input channels).  Operand layout of
+// Convolution as an implicit GEMM: a wave computes 16 pixels x 16 output channels with nine
+// v_mfma_f32_16x16x16_bf16 (one per tap, K = 16 input channels), its A operands read from an
+// LDS copy of the block's input patch.  Operand layout of
 // that instruction (64 lanes): lane l holds A[l%16][4(l/16) .. +3] and B[4(l/16) .. +3][l%16]
 // and receives D[4(l/16) .. +3][l%16].  Here A[i][k] = input channel k of pixel i shifted by
 // the tap, B[k][j] = weight (tap, k -> j), D[i][j] = output channel j of pixel i.
@@ -39,71 +40,84 @@ __device__ __forceinline__ int find_seg(const CnnSegs& s, int p) {
     return k;
 }
 
-// A operand for tap (dy, dx): four input channels of the lane's pixel, shifted; 0 outside
-// the image.  If `mask` is set the values are kept only where mask > 0 (ReLU derivative).
-__device__ __forceinline__ s4 load_a(const uint16_t* in, const uint16_t* mask, int base, int rows,
-                                     int cols, int y, int x, int dy, int dx, int c0, bool valid) {
-    s4 a = {0, 0, 0, 0};
-    const int yy = y + dy, xx = x + dx;
-    if (valid && yy >= 0 && yy < rows && xx >= 0 && xx < cols) {
-        const size_t off = ((size_t)base + (size_t)yy * cols + xx) * 16 + c0;
-        const uint2 v = *(const uint2*)(in + off);
-        a[0] = (short)(v.x & 0xffff);
-        a[1] = (short)(v.x >> 16);
-        a[2] = (short)(v.y & 0xffff);
-        a[3] = (short)(v.y >> 16);
-        if (mask) {
-            const uint2 m = *(const uint2*)(mask + off);
-            if (bf2f((uint16_t)(m.x & 0xffff)) <= 0.0f) a[0] = 0;
-            if (bf2f((uint16_t)(m.x >> 16)) <= 0.0f) a[1] = 0;
-            if (bf2f((uint16_t)(m.y & 0xffff)) <= 0.0f) a[2] = 0;
-            if (bf2f((uint16_t)(m.y >> 16)) <= 0.0f) a[3] = 0;
-        }
-    }
-    return a;
+// 3x3 convolution layer over all images.  A block of 4 waves computes a 16 x 16 pixel tile:
+// it stages the tile's 18 x 18 input patch (16 BF16 channels per pixel, zero outside the image,
+// optionally masked) in LDS, and each wave computes 4 rows of 16 pixels x 16 output channels,
+// nine MFMAs per row (one per tap) with the weights held in registers.
+constexpr int kConvTile = 16, kConvPatch = kConvTile + 2;
+
+__device__ __forceinline__ s4 unpack4(uint2 v) {
+    s4 r;
+    r[0] = (short)(v.x & 0xffff);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xffff);
+    r[3] = (short)(v.y >> 16);
+    return r;
 }
 
-// 3x3 convolution layer over all segments.  One wave per 16 pixels.
 template <bool OUT_F32>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int g = (blockIdx.x * 256 + threadIdx.x) >> 6;     // 16-pixel group
-    const int p0 = g * 16;
-    if (p0 >= a.segs.total) return;                          // whole wave exits together
-    const int sgi = find_seg(a.segs, p0);
+    __shared__ uint2 patch[kConvPatch * kConvPatch * 4];   // [y][x][channel quad]
+    const int b = blockIdx.x;
+    int sgi = 0;
+    while (sgi + 1 < a.segs.n && a.tblk[sgi + 1] <= b) ++sgi;
     const int base = a.segs.base[sgi], rows = a.segs.rows[sgi], cols = a.segs.cols[sgi];
-    const int npx = rows * cols;
-    // A-operand pixel of this lane
-    const int ia = p0 - base + (lane & 15);
-    const bool va = ia < npx;
-    const int ya = va ? ia / cols : 0, xa = va ? ia - ya * cols : 0;
-    const int c0 = 4 * (lane >> 4);
-    f4 acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const s4 av = load_a(a.in, a.mask, base, rows, cols, ya, xa, dy, dx, c0, va);
-        // B: weight[tap t][out j = lane%16][in 4(lane/16)..+3]
-        const uint2 wv = *(const uint2*)(a.w + ((size_t)t * 16 + (lane & 15)) * 16 + c0);
-        s4 bv;
-        bv[0] = (short)(wv.x & 0xffff);
-        bv[1] = (short)(wv.x >> 16);
-        bv[2] = (short)(wv.y & 0xffff);
-        bv[3] = (short)(wv.y >> 16);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    const int t = b - a.tblk[sgi];
+    const int tiles_x = (cols + kConvTile - 1) / kConvTile;
+    const int ty0 = (t / tiles_x) * kConvTile, tx0 = (t % tiles_x) * kConvTile;
+    for (int q = threadIdx.x; q < kConvPatch * kConvPatch * 4; q += 256) {
+        const int px = q >> 2, quad = q & 3;
+        const int yy = ty0 - 1 + px / kConvPatch, xx = tx0 - 1 + px % kConvPatch;
+        uint2 v = make_uint2(0u, 0u);
+        if (yy >= 0 && yy < rows && xx >= 0 && xx < cols) {
+            const size_t off = ((size_t)base + (size_t)yy * cols + xx) * 16 + quad * 4;
+            v = *(const uint2*)(a.in + off);
+            if (a.mask) {
+                const uint2 m = *(const uint2*)(a.mask + off);
+                if (bf2f((uint16_t)(m.x & 0xffff)) <= 0.0f) v.x &= 0xffff0000u;
+                if (bf2f((uint16_t)(m.x >> 16)) <= 0.0f) v.x &= 0x0000ffffu;
+                if (bf2f((uint16_t)(m.y & 0xffff)) <= 0.0f) v.y &= 0xffff0000u;
+                if (bf2f((uint16_t)(m.y >> 16)) <= 0.0f) v.y &= 0x0000ffffu;
+            }
+        }
+        patch[q] = v;
     }
-    const int j = lane & 15;
-    const float bias = a.bias ? a.bias[j] : 0.0f;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15;           // A row: pixel column within the tile; D column: channel
+    const int quad = lane >> 4;          // A/B k block: input channels 4 quad .. +3
+    // B: weight[tap][out j = lane % 16][in 4 (lane / 16) .. +3]
+    s4 bv[9];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = p0 - base + 4 * (lane >> 4) + r;
-        if (i >= npx) continue;
-        float v = acc[r] + bias;
-        if (a.relu) v = fmaxf(v, 0.0f);
-        if (OUT_F32) {
-            if (j < a.nout) a.out_f32[(size_t)j * a.segs.total + base + i] = v;
-        } else {
-            a.out[((size_t)base + i) * 16 + j] = j < a.nout ? f2bf(v) : (uint16_t)0;
+    for (int tp = 0; tp < 9; ++tp)
+        bv[tp] = unpack4(*(const uint2*)(a.w + ((size_t)tp * 16 + col) * 16 + 4 * quad));
+    const float bias = a.bias ? a.bias[col] : 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < kConvTile / 4; ++rr) {
+        const int row = wave * (kConvTile / 4) + rr;     // tile row of this wave
+        f4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int tp = 0; tp < 9; ++tp) {
+            const int dy = tp / 3 - 1, dx = tp % 3 - 1;
+            const s4 av = unpack4(patch[((row + 1 + dy) * kConvPatch + (col + 1 + dx)) * 4 + quad]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[tp], acc, 0, 0, 0);
+        }
+        // D[4 (lane / 16) + r][lane % 16]: pixel column 4 quad + r of this row, channel col
+        const int y = ty0 + row;
+        if (y >= rows) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = tx0 + 4 * quad + r;
+            if (x >= cols) continue;
+            const size_t i = (size_t)y * cols + x;
+            float v = acc[r] + bias;
+            if (a.relu) v = fmaxf(v, 0.0f);
+            if (OUT_F32) {
+                if (col < a.nout) a.out_f32[(size_t)col * a.segs.total + base + i] = v;
+            } else {
+                a.out[((size_t)base + i) * 16 + col] = col < a.nout ? f2bf(v) : (uint16_t)0;
+            }
         }
     }
 }
@@ -302,9 +316,15 @@ hipError_t launch_planes_out(const CnnSegs& sg, const float* src, int C, float* 
     return hipGetLastError();
 }
 
-hipError_t launch_conv(const ConvArgs& a, bool out_f32, hipStream_t s) {
-    const int groups = (a.segs.total + 15) / 16;
-    const int blocks = (groups + 3) / 4;
+hipError_t launch_conv(const ConvArgs& args, bool out_f32, hipStream_t s) {
+    ConvArgs a = args;
+    int blocks = 0;
+    for (int k = 0; k < a.segs.n; ++k) {
+        a.tblk[k] = blocks;
+        blocks += ((a.segs.rows[k] + kConvTile - 1) / kConvTile) *
+                  ((a.segs.cols[k] + kConvTile - 1) / kConvTile);
+    }
+    a.tblk[a.segs.n] = blocks;
     if (blocks == 0) return hipSuccess;
     if (out_f32)
         hipLaunchKernelGGL(k_conv<true>, dim3(blocks), dim3(256), 0, s, a);
