@@ -245,7 +245,7 @@ def cpu_baseline(wl_name, budget_s=20.0):
     with threadpool_limits(limits=1):
         o = Oracle(seq.rows, seq.cols, wl["levels"], wl["max_flow_px"], wl["smooth"],
                    c.fx, c.fy, c.cx, c.cy)
-        Y, R, _ = render_sequence(seq, range(min(8, seq.n_frames)))
+        Y, R, _ = render_sequence(seq, range(min(20, seq.n_frames)))
         o.push(Y[0].astype(np.float32), R[0].astype(np.float32), seq.dt)   # first frame: init
         t0 = time.perf_counter()
         k = 1
