@@ -413,6 +413,23 @@ def main():
             forms[f"batched_{rb['storage']}"] = rb
             print(f"[bench] batched {rb['storage']}: {rb['aggregate_frames_per_s']:.1f} "
                   f"stream-frames/s ({rb['mpix_per_s']:.0f} Mpix/s)", flush=True)
+        rd = run_gpu("driving2048x1024", max(10, args.steps // 2), max(2, args.warmup // 2),
+                     storage=1)
+        ld = level_table(rd["seq"].rows, rd["seq"].cols, rd["wl"]["levels"], rd["wl"]["max_flow_px"],
+                         rd["wl"]["smooth"])
+        msd = rd["kernel_ms"][1] / max(1, rd["kernel_n"][1])   # per level-step launch
+        launches = rd["kernel_n"][1] / max(1, max(10, args.steps // 2))
+        forms["large_2048x1024_fp16"] = {
+            "frames_per_s": max(10, args.steps // 2) / rd["elapsed"],
+            "level_step_us_per_frame": msd * launches * 1e3,
+            "level_step_launches_per_frame": launches,
+            "level_step_hbm_gbs": sum(L["rows"] * L["cols"] * step_bytes_per_px(L["top"], 2)
+                                      for L in ld) / (msd * launches * 1e-3) / 1e9,
+            "workload": "2048x1024, 4 levels, max flow 16 px (N=16/8/4/2), driving scene, "
+                        "FP16 storage",
+        }
+        print(f"[bench] large 2048x1024 fp16: {forms['large_2048x1024_fp16']['frames_per_s']:.1f} "
+              f"frames/s", flush=True)
         rl = run_learned(16, max(5, args.steps // 5), 2)
         forms["learned_16x512"] = rl
         print(f"[bench] learned 16x512: {rl['learned']['aggregate_frames_per_s']:.1f} "

@@ -187,3 +187,54 @@ def test_fp16_storage_plane64():
     w = _run(list(zip(Y, rho)), 64, 64, 1, wl["max_flow_px"], wl["smooth"],
              (c.fx, c.fy, c.cx, c.cy), storage=1, dts=[seq.dt] * len(Y), bar=FP16_EPE)
     log("plane64 fp16 worst mean EPE", w)
+
+
+def _workload_frames(name, n):
+    """The first n frames of a named workload, rendered on the GPU, as float32 host arrays."""
+    import torch
+    from synth.workloads import workload
+    wl = workload(name)
+    seq = wl["build"]("cuda")
+    out = []
+    for k in range(n):
+        f = seq.frame(k, "cuda")
+        out.append((f.Y.to(torch.float32).cpu().numpy(), f.rho.to(torch.float32).cpu().numpy()))
+    return wl, seq, out
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_boxes512_workload(storage):
+    """The bench's 512x512 three-level workload at full size, in the bench's launch
+    configuration: every pixel of the first frames against the oracle."""
+    wl, seq, frames = _workload_frames("boxes512", 4)
+    c = seq.camera
+    bar = FP32_EPE if storage == 0 else FP16_EPE
+    w = _run(frames, seq.rows, seq.cols, wl["levels"], wl["max_flow_px"], wl["smooth"],
+             (c.fx, c.fy, c.cx, c.cy), storage=storage, dts=[seq.dt] * 4, bar=bar)
+    log("boxes512 storage", storage, "worst mean EPE", w)
+
+
+def test_driving_2048x1024_fp16():
+    """The 2048x1024 four-level workload with a 16 px maximum flow (finest-level prediction in
+    two passes), FP16 storage, at full size in the bench's launch configuration.  The oracle
+    runs on a 576x576 crop (aligned to the coarsest level, principal point shifted), whose
+    pixels more than 160 px from the crop's edge depend on nothing outside it after one
+    update; those are compared."""
+    from oracle import Filter as Oracle
+    from paper_2406_18031_amd import sflow
+    wl, seq, frames = _workload_frames("driving2048x1024", 2)
+    c = seq.camera
+    H, mf, sm = wl["levels"], wl["max_flow_px"], wl["smooth"]
+    g = sflow.Filter(seq.rows, seq.cols, H, mf, sm, c.fx, c.fy, c.cx, c.cy, storage=1)
+    y0, x0, n, m = 224, 736, 576, 160
+    o = Oracle(n, n, H, mf, sm, c.fx, c.fy, c.cx - x0, c.cy - y0)
+    for k, (Y, rho) in enumerate(frames):
+        log(f"  frame {k} 2048x1024 H={H} FP16; oracle on the crop")
+        g.push(to_dev(Y, "float16"), to_dev(rho, "float16"), seq.dt)
+        o.push(rounded(Y, 1)[y0:y0 + n, x0:x0 + n], rounded(rho, 1)[y0:y0 + n, x0:x0 + n], seq.dt)
+        wg = gpu_flow_frame(g)[y0 + m:y0 + n - m, x0 + m:x0 + n - m]
+        wo = o.flow("w_frame")[m:n - m, m:n - m]
+        e = epe_px(wg, wo, o.grids[0].dmu[m:n - m, m:n - m])
+        log(f"    mean EPE {e['mean']:.2e} max {e['max']:.2e}")
+        assert e["mean"] <= FP16_EPE, (k, e)
+    g.close()
