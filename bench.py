@@ -141,6 +141,18 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
         for s_ in range(len(specs)):
             sflow.sf_get_flow_stream(b.ctx, s_, sflow.SF_FLOW_W_RAD_S, outs[s_])
 
+    # launch shape from the autotuner (pass length; tiles of the largest stream's levels)
+    from paper_2406_18031_amd import tune
+    big = max(specs, key=lambda sp: sp["rows"] * sp["cols"])
+    lv = []
+    r_, c_ = big["rows"], big["cols"]
+    for h in range(big["levels"]):
+        lv.append(dict(rows=r_, cols=c_, max_flow_px=big["max_flow_px"], smooth=big["smooth"][h],
+                       h=h))
+        r_, c_ = (r_ + 1) // 2, (c_ + 1) // 2
+    setting = tune.tune(b.ctx, lambda k: b.push([y[k % frames] for y in Ys],
+                                                [r[k % frames] for r in Rs], dts), lv)
+
     for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
@@ -162,7 +174,7 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
             npx = L["rows"] * L["cols"]
             step_bytes += npx * step_bytes_per_px(L["top"], 2 if storage == 1 else 4)
             step_flops += npx * step_flops_per_px(L["top"], L["N"], L["Ns"])
-    step_s = ms[1] / max(1, n[1]) * 1e-3
+    step_s = ms[1] / max(1, steps) * 1e-3          # level-step time per frame (all passes)
     sizes = {}
     for sp in specs:
         sizes[sp["rows"]] = sizes.get(sp["rows"], 0) + 1
@@ -176,6 +188,7 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
                                 zip(("pyramid", "level_step", "reconstruct"), ms)},
         "level_step_tflops": step_flops / step_s / 1e12,
         "level_step_hbm_gbs": step_bytes / step_s / 1e9,
+        "tuned": {"pass_steps": setting["pass_steps"], "tiles": setting["tiles"]},
     }
 
 

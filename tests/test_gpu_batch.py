@@ -93,3 +93,40 @@ def test_batch_call_rules():
     with pytest.raises(sflow.SflowError) as e:
         sflow.sf_create_batch([sflow.make_config(16, 16, 1, 1.0, [1])] * 65)
     assert e.value.status == sflow.SF_ERR_INVALID_ARG
+
+
+def test_autotuned_launch_shape_keeps_results():
+    """The autotuner only changes tiles and pass lengths, which never change the result: a
+    tuned batch gives bitwise the output of an untuned one."""
+    from paper_2406_18031_amd import sflow, tune
+    rng = np.random.default_rng(41)
+    specs = SPECS[:3]
+    frames = [_frames(rng, sp, 5) for sp in specs]
+    dev = [[(to_dev(Y), to_dev(r)) for Y, r in fr] for fr in frames]
+    dts = [0.01] * len(specs)
+    plain = sflow.Batch(specs)
+    tuned = sflow.Batch(specs)
+
+    def push(b, k):
+        b.push([d[k % 5][0] for d in dev], [d[k % 5][1] for d in dev], dts)
+
+    big = specs[2]
+    lv, r_, c_ = [], big["rows"], big["cols"]
+    for h in range(big["levels"]):
+        lv.append(dict(rows=r_, cols=c_, max_flow_px=big["max_flow_px"], smooth=big["smooth"][h],
+                       h=h))
+        r_, c_ = (r_ + 1) // 2, (c_ + 1) // 2
+    setting = tune.tune(tuned.ctx, lambda k: push(tuned, k), lv, pass_steps=(3, 8), frames=2,
+                        warmup=1)
+    log("tuned:", {k: v for k, v in setting.items() if k != "trials"})
+    # restart both streams from the same first frame
+    cams = [sp["camera"] for sp in specs]
+    sflow.sf_set_cameras(plain.ctx, cams)
+    sflow.sf_set_cameras(tuned.ctx, cams)
+    for k in range(5):
+        push(plain, k)
+        push(tuned, k)
+        for s in range(len(specs)):
+            a = plain.flow(s, sflow.SF_FLOW_W_FRAME).cpu().numpy()
+            b = tuned.flow(s, sflow.SF_FLOW_W_FRAME).cpu().numpy()
+            assert np.array_equal(a, b), (k, s)
