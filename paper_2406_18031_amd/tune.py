@@ -1,8 +1,8 @@
 """Autotuning of the level-step launch shape: steps per prediction pass and per-level tiles.
 
-Host logic over the C ABI (sf_set_pass_steps, sf_set_tile, sf_set_timing, sf_kernel_times):
-candidate settings are applied to a live context, a few frames are pushed with each, and the
-setting with the lowest level-step time per frame is kept.  Every candidate computes the same
+Host logic over the C ABI (sf_set_pass_steps, sf_set_tile): candidate settings are applied to
+a live context, a few frames are pushed with each, and the setting with the lowest wall time
+per frame is kept.  Every candidate computes the same
 result (tile shapes and pass splits change only which block computes a pixel), so tuning never
 changes the output.  Results can be cached in a JSON file keyed by the device and the streams'
 configuration.
@@ -42,15 +42,18 @@ def tile_candidates(rows: int, cols: int, halo: int) -> List[Tuple[int, int]]:
 
 
 def _frame_time(ctx: int, push: Callable[[int], None], frames: int, warmup: int) -> float:
+    """wall milliseconds per frame (the level steps of a frame overlap on two streams, so the
+    sum of kernel times is not the frame's time)"""
+    import time
+    import torch
     for k in range(warmup):
         push(k)
-    sflow.sf_set_timing(ctx, True)
-    sflow.sf_kernel_times(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     for k in range(frames):
         push(warmup + k)
-    ms, n = sflow.sf_kernel_times(ctx, reset=True)
-    sflow.sf_set_timing(ctx, False)
-    return ms[1] / max(1, frames)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / max(1, frames)
 
 
 def tune(ctx: int, push: Callable[[int], None], levels: Sequence[dict],
