@@ -258,6 +258,7 @@ sf_status sf_net_train_step(sf_net net, const float* in, const float* target, fl
 /* the loss's eps (pixels, > 0; default 1e-3: close to the endpoint error itself; about 1
  * makes the loss quadratic for errors below a pixel) */
 sf_status sf_net_set_loss(sf_net net, float eps);
+/* releases the network and its device memory (synchronises its stream); NULL is a no-op */
 sf_status sf_net_destroy(sf_net net);
 const char* sf_net_last_error(sf_net net);
 

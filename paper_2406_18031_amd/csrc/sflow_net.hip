@@ -340,7 +340,7 @@ sf_status sf_net_set_loss(sf_net n, float eps) {
 }
 
 sf_status sf_net_destroy(sf_net n) {
-    if (!n) return nfail(nullptr, SF_ERR_INVALID_ARG, "NULL network");
+    if (!n) return SF_OK;
     if (!n->hip_failed) (void)hipStreamSynchronize(n->stream);
     if (n->mem) (void)hipFree(n->mem);
     delete n;

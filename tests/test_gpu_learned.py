@@ -250,3 +250,36 @@ def test_learned_needs_parameters():
     with pytest.raises(sflow.SflowError) as e:
         plain.set_learned(learned.init_params(0), 1.0)
     assert e.value.status == sflow.SF_ERR_STATE
+
+
+def test_network_object_errors():
+    """The trainer's calls validate their arguments before any device work."""
+    import ctypes
+    from paper_2406_18031_amd import learned, sflow
+    lib = sflow.lib
+    out = ctypes.c_void_p()
+    rows = (ctypes.c_int32 * 1)(8)
+    cols = (ctypes.c_int32 * 1)(8)
+    assert lib.sf_net_create(rows, cols, 0, None, ctypes.byref(out)) == sflow.SF_ERR_INVALID_ARG
+    bad = (ctypes.c_int32 * 1)(0)
+    assert lib.sf_net_create(bad, cols, 1, None, ctypes.byref(out)) == sflow.SF_ERR_INVALID_ARG
+    net = sflow.Net([(8, 8)], learned.init_params(0))
+    p = learned.init_params(0)
+    assert lib.sf_net_set_params(net.net, p.ctypes.data, p.size - 1) == sflow.SF_ERR_INVALID_ARG
+    pn = p.copy()
+    pn[5] = np.inf
+    assert lib.sf_net_set_params(net.net, pn.ctypes.data, pn.size) == sflow.SF_ERR_INVALID_ARG
+    x = to_dev(np.zeros(9 * 64))
+    t = to_dev(np.zeros(3 * 64))
+    host = np.zeros(9 * 64, np.float32)
+    assert lib.sf_net_train_step(net.net, host.ctypes.data, t.data_ptr(), 1e-3, None, None) == \
+        sflow.SF_ERR_INVALID_ARG
+    assert lib.sf_net_train_step(net.net, x.data_ptr(), t.data_ptr(), -1.0, None, None) == \
+        sflow.SF_ERR_INVALID_ARG
+    assert lib.sf_net_set_loss(net.net, 0.0) == sflow.SF_ERR_INVALID_ARG
+    # a valid step still works after the rejected calls, and leaves finite parameters
+    loss, grad = net.train_step(x, t, 1e-3, want_grad=True)
+    assert np.isfinite(loss) and np.all(np.isfinite(grad))
+    assert np.all(np.isfinite(net.params()))
+    net.close()
+    assert lib.sf_net_destroy(None) == sflow.SF_OK
