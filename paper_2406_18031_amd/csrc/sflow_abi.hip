@@ -287,6 +287,26 @@ static ElemArgs elem_args(sf_ctx c, int level, int parity) {
     return a;
 }
 
+// A two-level tile launch (pyramid, reconstruction) at `level` over the streams with more than
+// level + above levels.
+static ElemArgs tile_args(sf_ctx c, int level, int above, int parity) {
+    ElemArgs a{};
+    a.lv = c->lv_dev;
+    a.parity = parity;
+    int b = 0;
+    for (int s = 0; s < c->S; ++s) {
+        const StreamInfo& si = c->st[s];
+        if (level + above >= si.H) continue;
+        const int e = si.e0 + level;
+        a.ent[a.n] = e;
+        a.blk[a.n] = b;
+        b += ((c->lv[e].rows + kTile2 - 1) / kTile2) * ((c->lv[e].cols + kTile2 - 1) / kTile2);
+        ++a.n;
+    }
+    a.blk[a.n] = b;
+    return a;
+}
+
 extern "C" {
 
 sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf_ctx* out) {
@@ -783,9 +803,9 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         const double dp = c->st[s].dt_prev;
         in.scale[s] = (c->frames == 0 || dt[s] == dp) ? 1.0f : (float)(dt[s] / dp);
     }
-    // pyramid, finest to coarsest: one launch per depth for all streams
-    for (int h = 1; h < c->max_levels; ++h) {
-        ElemArgs a = elem_args(c, h, 0);
+    // pyramid, finest to coarsest: one launch per two depths (d, d + 1) for all streams
+    for (int h = 1; h < c->max_levels; h += 2) {
+        ElemArgs a = tile_args(c, h, 0, 0);
         a.in = in;
         TimedLaunch t(c, 0);
         HIP_TRY(c, launch_pyramid(c->storage, a, c->stream));
@@ -814,22 +834,10 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
             sf_status s2 = run_learned(c, q);
             if (s2 != SF_OK) return s2;
         }
-        for (int h = c->max_levels - 2; h >= 0; --h) {
-            // reconstruction of level h for the streams where h is below the top
-            ElemArgs r{};
-            r.lv = c->lv_dev;
-            r.parity = q;
-            int b = 0;
-            for (int s = 0; s < c->S; ++s) {
-                const StreamInfo& si = c->st[s];
-                if (h >= si.H - 1) continue;
-                const int e = si.e0 + h;
-                r.ent[r.n] = e;
-                r.blk[r.n] = b;
-                b += (c->lv[e].rows * c->lv[e].cols + kElemBlock - 1) / kElemBlock;
-                ++r.n;
-            }
-            r.blk[r.n] = b;
+        // reconstruction, coarse to fine: one launch per two levels (h + 1, h), h even, for
+        // the streams where h is below the top
+        for (int h = (c->max_levels - 2) & ~1; h >= 0; h -= 2) {
+            ElemArgs r = tile_args(c, h, 1, q);
             TimedLaunch t(c, 2);
             HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
             t.done();

@@ -29,6 +29,8 @@ constexpr int kLearnXS = 26;      // smoothed least-squares solution (the state)
 constexpr int kLearnCorr = 29;    // applied correction, rad/frame (0 where it fell back)
 constexpr int kLearnPlanes = 32;
 constexpr int kElemBlock = 256;      // threads (pixels) per block of the per-pixel kernels
+constexpr int kTile2 = 16;           // tile side of the two-level pyramid / reconstruction kernels
+static_assert(kTile2 * kTile2 == kElemBlock, "one thread per tile pixel");
 
 // Parameters of one pyramid level of one camera stream ("entry"), uploaded to device memory
 // whenever the camera or the tiling changes.  Entries are ordered stream by stream, finest
@@ -80,7 +82,8 @@ struct StepArgs {
 };
 
 // A launch of a per-pixel kernel over a list of entries: entry ent[k] owns blocks
-// [blk[k], blk[k+1]) of kElemBlock pixels each.
+// [blk[k], blk[k+1]) of kElemBlock pixels each (of kTile2 x kTile2 tiles for the pyramid and
+// reconstruction kernels).
 struct ElemArgs {
     const LevelDev* lv;
     int n;

@@ -664,36 +664,117 @@ __device__ __forceinline__ bool elem_pixel(const ElemArgs& a, int& e, int& i, in
 
 // ------------------------------------------------------------------------------------------
 // pyramid: level h+1 = 5x5 Gaussian blur of level h sampled at (2i, 2j); inverse depth
-// blurred over valid samples only (missing if none).  The entry is the destination level.
+// blurred over valid samples only (missing if none).
 // ------------------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kElemBlock) k_pyramid(ElemArgs a) {
-    int e, i, j;
-    if (!elem_pixel(a, e, i, j)) return;
-    const LevelDev& D = a.lv[e];
-    const LevelDev& S = a.lv[D.child];
-    const bool fin = S.level == 0;
-    const T* Ys = (const T*)(fin ? a.in.Y[D.stream] : S.Ym);
-    const T* Rs = (const T*)(fin ? a.in.R[D.stream] : S.Rm);
-    const int sp = fin ? S.cols : S.pitch;
+template <typename T> __device__ __forceinline__ float rnd(float v);   // value as stored
+template <> __device__ __forceinline__ float rnd<float>(float v) { return v; }
+template <> __device__ __forceinline__ float rnd<__half>(float v) {
+    return __half2float(__float2half(v));
+}
+
+// The entry and tile of a two-level tile launch.
+__device__ __forceinline__ int tile_entry(const ElemArgs& a, int& t) {
+    const int b = blockIdx.x;
+    int k = 0;
+    while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
+    t = b - a.blk[k];
+    return a.ent[k];
+}
+
+// One pyramid sample of a level from the level below it; `ld(ii, jj, y, r)` reads the finer
+// level at (ii, jj), already clamped.  Both phases of k_pyramid use it, so a level computed in
+// LDS and one read from memory are summed in the same order.
+template <class Load>
+__device__ __forceinline__ void pyr_sample(Load ld, int i, int j, int rows, int cols, float& y,
+                                           float& r) {
     float acc = 0.0f, num = 0.0f, den = 0.0f;
 #pragma unroll
     for (int aa = -2; aa <= 2; ++aa) {
-        const size_t row = (size_t)clampi(2 * i + aa, 0, S.rows - 1) * sp;
+        const int ii = clampi(2 * i + aa, 0, rows - 1);
 #pragma unroll
         for (int bb = -2; bb <= 2; ++bb) {
             const float w = gtap(aa) * gtap(bb);
-            const size_t idx = row + clampi(2 * j + bb, 0, S.cols - 1);
-            acc = fmaf(w, ldv(Ys, idx), acc);
-            const float r = ldv(Rs, idx);
-            if (!isnan(r)) {
-                num = fmaf(w, r, num);
+            float ys, rs;
+            ld(ii, clampi(2 * j + bb, 0, cols - 1), ys, rs);
+            acc = fmaf(w, ys, acc);
+            if (!isnan(rs)) {
+                num = fmaf(w, rs, num);
                 den += w;
             }
         }
     }
-    stv((T*)D.Ym, (size_t)i * D.pitch + j, acc);
-    stv((T*)D.Rm, (size_t)i * D.pitch + j, den > 0.0f ? num / den : __int_as_float(0x7fc00000));
+    y = acc;
+    r = den > 0.0f ? num / den : __int_as_float(0x7fc00000);
+}
+
+// Two pyramid levels per launch: the entry is level d (>= 1).  A block owns a kTile2 x kTile2
+// tile of level d and, if level d + 1 exists, the kTile2/2 x kTile2/2 tile of level d + 1
+// above it.  Phase 1 computes level d on the tile plus the rows and columns that level d + 1
+// reads (at most kTile2 + 3 per side, one pixel per thread) into LDS, as stored (rounded to
+// T), and writes the tile's own pixels; phase 2 computes level d + 1 from LDS.  Every level-d
+// pixel is written by exactly one block.
+constexpr int kPyrPatch = kTile2 + 3;
+constexpr int kPyrThreads = 512;
+static_assert(kPyrPatch * kPyrPatch <= kPyrThreads, "one patch pixel per thread");
+template <typename T>
+__global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
+    constexpr int P = kPyrPatch;
+    __shared__ float pY[P][P + 1], pR[P][P + 1];
+    int t;
+    const LevelDev& D = a.lv[tile_entry(a, t)];
+    const LevelDev& S = a.lv[D.child];
+    const int ntx = (D.cols + kTile2 - 1) / kTile2;
+    const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
+    const bool two = D.parent >= 0;
+    int r0 = ti0, r1 = min(ti0 + kTile2, D.rows), q0 = tj0, q1 = min(tj0 + kTile2, D.cols);
+    int a2 = 0, b2 = 0, c2 = 0, d2 = 0;
+    if (two) {
+        const LevelDev& U = a.lv[D.parent];
+        a2 = ti0 / 2;
+        b2 = min(a2 + kTile2 / 2, U.rows);
+        c2 = tj0 / 2;
+        d2 = min(c2 + kTile2 / 2, U.cols);
+        r0 = min(r0, max(2 * a2 - 2, 0));
+        r1 = max(r1, min(2 * b2 + 1, D.rows));
+        q0 = min(q0, max(2 * c2 - 2, 0));
+        q1 = max(q1, min(2 * d2 + 1, D.cols));
+    }
+    const int nr = r1 - r0, nc = q1 - q0;
+    const bool fin = S.level == 0;
+    const T* Ys = (const T*)(fin ? a.in.Y[D.stream] : S.Ym);
+    const T* Rs = (const T*)(fin ? a.in.R[D.stream] : S.Rm);
+    const int sp = fin ? S.cols : S.pitch;
+    const int p = threadIdx.x;
+    if (p < nr * nc) {
+        const int li = p / nc, lj = p - li * nc;
+        const int i = r0 + li, j = q0 + lj;
+        auto from_mem = [&](int ii, int jj, float& y, float& r) {
+            const size_t idx = (size_t)ii * sp + jj;
+            y = ldv(Ys, idx);
+            r = ldv(Rs, idx);
+        };
+        float y, r;
+        pyr_sample(from_mem, i, j, S.rows, S.cols, y, r);
+        pY[li][lj] = rnd<T>(y);
+        pR[li][lj] = rnd<T>(r);
+        if (i >= ti0 && i < ti0 + kTile2 && j >= tj0 && j < tj0 + kTile2) {
+            stv((T*)D.Ym, (size_t)i * D.pitch + j, y);
+            stv((T*)D.Rm, (size_t)i * D.pitch + j, r);
+        }
+    }
+    if (!two) return;
+    __syncthreads();
+    const LevelDev& U = a.lv[D.parent];
+    const int i = a2 + p / (kTile2 / 2), j = c2 + p % (kTile2 / 2);
+    if (p >= (kTile2 / 2) * (kTile2 / 2) || i >= b2 || j >= d2) return;
+    auto from_lds = [&](int ii, int jj, float& y, float& r) {
+        y = pY[ii - r0][jj - q0];
+        r = pR[ii - r0][jj - q0];
+    };
+    float y, r;
+    pyr_sample(from_lds, i, j, D.rows, D.cols, y, r);
+    stv((T*)U.Ym, (size_t)i * U.pitch + j, y);
+    stv((T*)U.Rm, (size_t)i * U.pitch + j, r);
 }
 
 // first frame: Yhat = G * Y, rho = measured (0 where missing), w = dw = 0, into state[0]
@@ -730,27 +811,73 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
 }
 
 // reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[parity]
-template <typename T>
-__global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
-    int e, i, j;
-    if (!elem_pixel(a, e, i, j)) return;
-    const LevelDev& L = a.lv[e];
-    const LevelDev& U = a.lv[L.parent];
-    const int q = a.parity;
+// Bilinear sample of the coarser level at fine pixel (i, j); `W(ii, jj)` reads it as stored.
+template <class Load>
+__device__ __forceinline__ float bilerp_up(Load W, int i, int j, int urows, int ucols) {
     const int i0 = i >> 1, j0 = j >> 1;
-    const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
+    const int i1 = min(i0 + 1, urows - 1), j1 = min(j0 + 1, ucols - 1);
     const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
     const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
     const float w10 = fi * (1.0f - fj), w11 = fi * fj;
+    return w00 * W(i0, j0) + w01 * W(i0, j1) + w10 * W(i1, j0) + w11 * W(i1, j1);
+}
+
+// Two reconstruction levels per launch: the entry is level h, U its parent.  A block owns a
+// kTile2 x kTile2 tile of level h.  Phase 1 holds U on the tile's footprint (at most
+// kTile2/2 + 1 per side) in LDS, as stored: reconstructed from U's parent when U is not the
+// top level (the block then also writes the U pixels (i, j) with (2i, 2j) in its tile, so
+// every U pixel is written once), read from the state otherwise.  Phase 2 reconstructs level h.
+template <typename T>
+__global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
+    constexpr int P = kTile2 / 2 + 1;
+    __shared__ float pw[3][P][P + 1];
+    int t;
+    const LevelDev& L = a.lv[tile_entry(a, t)];
+    const LevelDev& U = a.lv[L.parent];
+    const int q = a.parity;
+    const int ntx = (L.cols + kTile2 - 1) / kTile2;
+    const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
+    const int ti1 = min(ti0 + kTile2, L.rows), tj1 = min(tj0 + kTile2, L.cols);
+    const int pa = ti0 >> 1, pb = min(((ti1 - 1) >> 1) + 2, U.rows);
+    const int pc = tj0 >> 1, pd = min(((tj1 - 1) >> 1) + 2, U.cols);
+    const int np = (pb - pa) * (pd - pc);
+    // level-h pixel of this thread, its increment loaded before the barrier
+    const int li = threadIdx.x / kTile2, lj = threadIdx.x % kTile2;
+    const int i = ti0 + li, j = tj0 + lj;
+    const bool own = i < ti1 && j < tj1;
+    const size_t go = (size_t)i * L.pitch + j;
+    float d[3] = {0.0f, 0.0f, 0.0f};
+    if (own)
+        for (int k = 0; k < 3; ++k) d[k] = ldv((const T*)L.dw[q][k], go);
+    if ((int)threadIdx.x < np) {
+        const int ui = pa + threadIdx.x / (pd - pc), uj = pc + threadIdx.x % (pd - pc);
+        const size_t uo = (size_t)ui * U.pitch + uj;
+        if (U.top) {
+            for (int k = 0; k < 3; ++k) pw[k][ui - pa][uj - pc] = ldv((const T*)U.w[q][k], uo);
+        } else {
+            const LevelDev& V = a.lv[U.parent];
+            const float vin = flow_in_scale<T>(V), uin = flow_in_scale<T>(U);
+            const float uout = flow_out_scale<T>(U);
+            const bool wr = 2 * ui >= ti0 && 2 * ui < ti1 && 2 * uj >= tj0 && 2 * uj < tj1;
+            for (int k = 0; k < 3; ++k) {
+                const T* W = (const T*)V.w[q][k];
+                auto ld = [&](int ii, int jj) { return ldv(W, (size_t)ii * V.pitch + jj); };
+                const float c = bilerp_up(ld, ui, uj, V.rows, V.cols);
+                const float v = (c * vin + ldv((const T*)U.dw[q][k], uo) * uin) * uout;
+                pw[k][ui - pa][uj - pc] = rnd<T>(v);
+                if (wr) stv((T*)U.w[q][k], uo, v);
+            }
+        }
+    }
+    __syncthreads();
+    if (!own) return;
     const float uin = flow_in_scale<T>(U);
     const float lin = flow_in_scale<T>(L);
     const float lout = flow_out_scale<T>(L);
-    const size_t go = (size_t)i * L.pitch + j;
     for (int k = 0; k < 3; ++k) {
-        const T* W = (const T*)U.w[q][k];
-        const float c = w00 * ldv(W, (size_t)i0 * U.pitch + j0) + w01 * ldv(W, (size_t)i0 * U.pitch + j1) +
-                        w10 * ldv(W, (size_t)i1 * U.pitch + j0) + w11 * ldv(W, (size_t)i1 * U.pitch + j1);
-        const float v = c * uin + ldv((const T*)L.dw[q][k], go) * lin;
+        auto ld = [&](int ii, int jj) { return pw[k][ii - pa][jj - pc]; };
+        const float c = bilerp_up(ld, i, j, U.rows, U.cols);
+        const float v = c * uin + d[k] * lin;
         stv((T*)L.w[q][k], go, v * lout);
     }
 }
@@ -962,9 +1089,9 @@ static int elem_blocks(const ElemArgs& a) { return a.blk[a.n]; }
 hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_pyramid<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+        hipLaunchKernelGGL(k_pyramid<__half>, dim3(elem_blocks(a)), dim3(kPyrThreads), 0, s, a);
     else
-        hipLaunchKernelGGL(k_pyramid<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+        hipLaunchKernelGGL(k_pyramid<float>, dim3(elem_blocks(a)), dim3(kPyrThreads), 0, s, a);
     return hipGetLastError();
 }
 
