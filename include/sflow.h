@@ -126,7 +126,11 @@ sf_status sf_set_camera(sf_ctx ctx, const sf_camera* cam);
  * measurement, 0 = infinitely far, valid), dt seconds since the previous frame (> 0,
  * finite; ignored on the first frame).  The first frame after sf_set_camera initialises the
  * state (flow 0, inverse depth from rho with 0 where missing; Section "Ground truth
- * evaluation").  Later frames run prediction, update, smoothing and reconstruction. */
+ * evaluation").  Later frames run prediction, update, smoothing and reconstruction; the
+ * reconstruction launch holding the finest level is enqueued by the next call that needs it
+ * (sf_get_flow, which runs it together with the output, or a push, state copy, tile or pass
+ * change, update-input read), always on the context's stream and before that call's own work,
+ * so the deferral is invisible to the caller. */
 sf_status sf_push_frame(sf_ctx ctx, const void* Y, const void* rho, double dt);
 
 /* Write the finest-level result of the last push to out (device, float32, see SF_FLOW_*).

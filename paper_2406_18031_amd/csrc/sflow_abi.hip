@@ -34,6 +34,9 @@ struct StreamInfo {
 
 struct sf_ctx_s {
     int S = 0;                     // streams
+    // The frame's last reconstruction launch (the one holding the finest levels) waits for the
+    // next call that needs them, so that sf_get_flow can run it together with the output.
+    bool recon_pending = false;
     int storage = SF_FP32;
     hipStream_t stream = nullptr;
     int esize = 4;                 // bytes per stored element
@@ -309,6 +312,8 @@ static ElemArgs tile_args(sf_ctx c, int level, int above, int parity) {
 
 extern "C" {
 
+static sf_status flush_recon(sf_ctx c);
+
 sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf_ctx* out) {
     if (!out) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL output pointer");
     *out = nullptr;
@@ -547,6 +552,7 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
         }
         si.dt_prev = 0.0;
     }
+    c->recon_pending = false;   // the state restarts
     sf_status s2 = upload_levels(c);
     if (s2 != SF_OK) return s2;
     c->camera = true;
@@ -578,6 +584,8 @@ sf_status sf_set_tile(sf_ctx c, int32_t level, int32_t tw, int32_t th) {
                             halo, kRegion);
         }
     }
+    st = flush_recon(c);
+    if (st != SF_OK) return st;
     c->user_tw[h] = tw;
     c->user_th[h] = th;
     if (c->camera) return upload_levels(c);
@@ -598,6 +606,8 @@ sf_status sf_set_pass_steps(sf_ctx c, int32_t steps) {
                             "pass exceeds the region", s, h + 1, halo, steps);
         }
     }
+    st = flush_recon(c);
+    if (st != SF_OK) return st;
     const int old = c->pass_steps;
     c->pass_steps = steps;
     if (c->camera) {
@@ -640,6 +650,18 @@ struct TimedLaunch {
         }
     }
 };
+
+// Runs the deferred reconstruction launch, if any.  Every entry point that reads or replaces
+// the finest levels' flow, or relays the levels out, calls it first.
+static sf_status flush_recon(sf_ctx c) {
+    if (!c->recon_pending) return SF_OK;
+    c->recon_pending = false;
+    ElemArgs r = tile_args(c, 0, 1, c->parity);
+    TimedLaunch t(c, 2);
+    HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
+    t.done();
+    return SF_OK;
+}
 
 sf_status sf_set_timing(sf_ctx c, int32_t enable) {
     sf_status st = check_alive(c);
@@ -769,6 +791,8 @@ sf_status sf_get_update_inputs(sf_ctx c, int32_t stream, float* out) {
     if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
     if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
     if (c->frames < 2) return fail(c, SF_ERR_STATE, "no update has run yet");
+    st = flush_recon(c);
+    if (st != SF_OK) return st;
     ElemArgs a{};
     a.lv = c->lv_dev;
     a.n = 1;
@@ -796,6 +820,8 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         if (!(dt[s] > 0.0) || !isfinite(dt[s]))
             return fail(c, SF_ERR_INVALID_ARG, "stream %d: dt must be > 0 and finite", s);
     }
+    st = flush_recon(c);
+    if (st != SF_OK) return st;
     FrameInputs in{};
     for (int s = 0; s < c->S; ++s) {
         in.Y[s] = Y[s];
@@ -836,12 +862,14 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         }
         // reconstruction, coarse to fine: one launch per two levels (h + 1, h), h even, for
         // the streams where h is below the top
-        for (int h = (c->max_levels - 2) & ~1; h >= 0; h -= 2) {
+        // (the launch holding level 0 is deferred: recon_pending)
+        for (int h = (c->max_levels - 2) & ~1; h > 0; h -= 2) {
             ElemArgs r = tile_args(c, h, 1, q);
             TimedLaunch t(c, 2);
             HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
             t.done();
         }
+        c->recon_pending = c->max_levels >= 2;
         c->parity = q;
     }
     for (int s = 0; s < c->S; ++s) c->st[s].dt_prev = dt[s];
@@ -864,6 +892,24 @@ sf_status sf_get_flow_stream(sf_ctx c, int32_t stream, int32_t kind, void* out) 
         return fail(c, SF_ERR_INVALID_ARG, "unknown flow kind %d", kind);
     if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
     if (!c->camera || c->frames == 0) return fail(c, SF_ERR_STATE, "no frame has been pushed");
+    const float inv_dt = (float)(1.0 / c->st[stream].dt_prev);
+    if (kind != SF_FLOW_RHO && c->recon_pending && c->st[stream].H >= 2) {
+        // the deferred reconstruction, writing this stream's output as it goes
+        c->recon_pending = false;
+        ElemArgs r = tile_args(c, 0, 1, c->parity);
+        r.kind = kind;
+        r.inv_dt = inv_dt;
+        r.out = (float*)out;
+        r.out_entry = c->st[stream].e0;
+        TimedLaunch t(c, 2);
+        HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
+        t.done();
+        return SF_OK;
+    }
+    if (kind != SF_FLOW_RHO) {   // the inverse depth does not depend on the reconstruction
+        st = flush_recon(c);
+        if (st != SF_OK) return st;
+    }
     ElemArgs a{};
     a.lv = c->lv_dev;
     a.n = 1;
@@ -872,7 +918,7 @@ sf_status sf_get_flow_stream(sf_ctx c, int32_t stream, int32_t kind, void* out) 
     a.blk[1] = (c->lv[a.ent[0]].rows * c->lv[a.ent[0]].cols + kElemBlock - 1) / kElemBlock;
     a.parity = c->parity;
     a.kind = kind;
-    a.inv_dt = (float)(1.0 / c->st[stream].dt_prev);
+    a.inv_dt = inv_dt;
     a.out = (float*)out;
     HIP_TRY(c, launch_output(c->storage, a, c->stream));
     return SF_OK;
@@ -1042,6 +1088,8 @@ sf_status sf_get_state_stream(sf_ctx c, int32_t stream, void* host_blob, size_t 
         memset((char*)host_blob + sizeof hd, 0, bytes - sizeof hd);
         return SF_OK;
     }
+    st = flush_recon(c);
+    if (st != SF_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return transfer_state(c, stream, true, (float*)((char*)host_blob + sizeof hd));
 }
@@ -1063,8 +1111,11 @@ sf_status sf_set_state_stream(sf_ctx c, int32_t stream, const void* host_blob, s
         return fail(c, SF_ERR_INVALID_ARG, "blob dt_prev must be > 0");
     if (c->S > 1 && (!hd.initialised || c->frames == 0))
         return fail(c, SF_ERR_STATE, "a batch takes states only once every stream has a frame");
+    st = flush_recon(c);   // the other streams' finest levels
+    if (st != SF_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (!hd.initialised) {
+        c->recon_pending = false;
         c->frames = 0;
         c->parity = 0;
         return SF_OK;

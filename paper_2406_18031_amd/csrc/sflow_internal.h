@@ -92,7 +92,8 @@ struct ElemArgs {
     int parity;                      // state parity read/written by the kernel
     int kind;                        // output kind (k_output)
     float inv_dt;                    // output scale to rad/s (k_output)
-    float* out;                      // output planes (k_output)
+    float* out;                      // output planes (k_output; k_reconstruct when set)
+    int out_entry;                   // k_reconstruct: the finest-level entry whose output it writes
     FrameInputs in;
 };
 

@@ -275,7 +275,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
 #pragma unroll
                 for (int k = 0; k < 3; ++k) F[r][k] = ldv((const T*)L.w[par][k], g) * fs;
                 F[r][KR] = ldv((const T*)L.rho[par], g);
-                if (!TOP) {
+                if constexpr (!TOP) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k) F[r][3 + k] = ldv((const T*)L.dw[par][k], g) * fs;
                     F[r][7] = ldv((const T*)L.Y[par], g);
@@ -810,6 +810,37 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
     }
 }
 
+// One output pixel of a stream's finest level from its flow (rad/frame, as stored): the kind
+// a.kind into the planes a.out.  The learned update's correction is added here.
+__device__ __forceinline__ void emit_flow(const ElemArgs& a, const LevelDev& L, int i, int j,
+                                          float wx, float wy, float wz) {
+    float* out = a.out;
+    const size_t plane = (size_t)L.rows * L.cols;
+    const size_t o = (size_t)i * L.cols + j;
+    if (L.learned) {   // the learned update's correction of the output
+        const float* lb = L.lbuf + L.lbase + o;
+        const size_t P = (size_t)L.ltotal;
+        wx += lb[kLearnCorr * P];
+        wy += lb[(kLearnCorr + 1) * P];
+        wz += lb[(kLearnCorr + 2) * P];
+    }
+    if (a.kind == SF_FLOW_W_RAD_S || a.kind == SF_FLOW_W_FRAME) {
+        const float m = a.kind == SF_FLOW_W_RAD_S ? a.inv_dt : 1.0f;
+        out[o] = wx * m;
+        out[o + plane] = wy * m;
+        out[o + 2 * plane] = wz * m;
+        return;
+    }
+    const Geo g = pixel_geo(L, i, j);
+    if (a.kind == SF_FLOW_TANGENT_PX) {
+        out[o] = flow_u(g, wx, wy, wz);
+        out[o + plane] = flow_v(g, wx, wy, wz);
+    } else {   // normal: <eta, w> / dmu with dmu = sqrt(1 - eta_x^2) / (fx |r_n|)
+        const float q2 = sqrtf(fmaf(g.y, g.y, 1.0f)) * g.rinv;
+        out[o] = normal_s(g, wx, wy, wz) * g.fxrn / q2;
+    }
+}
+
 // reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[parity]
 // Bilinear sample of the coarser level at fine pixel (i, j); `W(ii, jj)` reads it as stored.
 template <class Load>
@@ -826,13 +857,16 @@ __device__ __forceinline__ float bilerp_up(Load W, int i, int j, int urows, int 
 // kTile2 x kTile2 tile of level h.  Phase 1 holds U on the tile's footprint (at most
 // kTile2/2 + 1 per side) in LDS, as stored: reconstructed from U's parent when U is not the
 // top level (the block then also writes the U pixels (i, j) with (2i, 2j) in its tile, so
-// every U pixel is written once), read from the state otherwise.  Phase 2 reconstructs level h.
+// every U pixel is written once), read from the state otherwise.  Phase 2 reconstructs level h
+// and, for the entry a.out_entry when a.out is set, writes that stream's output (emit_flow),
+// bitwise what k_output would write after this launch.
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     constexpr int P = kTile2 / 2 + 1;
     __shared__ float pw[3][P][P + 1];
     int t;
-    const LevelDev& L = a.lv[tile_entry(a, t)];
+    const int e = tile_entry(a, t);
+    const LevelDev& L = a.lv[e];
     const LevelDev& U = a.lv[L.parent];
     const int q = a.parity;
     const int ntx = (L.cols + kTile2 - 1) / kTile2;
@@ -874,12 +908,15 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     const float uin = flow_in_scale<T>(U);
     const float lin = flow_in_scale<T>(L);
     const float lout = flow_out_scale<T>(L);
+    float w[3];
     for (int k = 0; k < 3; ++k) {
         auto ld = [&](int ii, int jj) { return pw[k][ii - pa][jj - pc]; };
         const float c = bilerp_up(ld, i, j, U.rows, U.cols);
         const float v = c * uin + d[k] * lin;
         stv((T*)L.w[q][k], go, v * lout);
+        w[k] = rnd<T>(v * lout) * lin;    // as k_output reads it back
     }
+    if (a.out && e == a.out_entry) emit_flow(a, L, i, j, w[0], w[1], w[2]);
 }
 
 // finest-level outputs of one stream (a single entry)
@@ -889,40 +926,14 @@ __global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
     if (!elem_pixel(a, e, i, j)) return;
     const LevelDev& L = a.lv[e];
     const int q = a.parity;
-    float* out = a.out;
     const size_t go = (size_t)i * L.pitch + j;
-    const size_t plane = (size_t)L.rows * L.cols;
-    const size_t o = (size_t)i * L.cols + j;
     if (a.kind == SF_FLOW_RHO) {
-        out[o] = ldv((const T*)L.rho[q], go);
+        a.out[(size_t)i * L.cols + j] = ldv((const T*)L.rho[q], go);
         return;
     }
     const float fs = flow_in_scale<T>(L);
-    float wx = ldv((const T*)L.w[q][0], go) * fs;
-    float wy = ldv((const T*)L.w[q][1], go) * fs;
-    float wz = ldv((const T*)L.w[q][2], go) * fs;
-    if (L.learned) {   // the learned update's correction of the output
-        const float* lb = L.lbuf + L.lbase + o;
-        const size_t P = (size_t)L.ltotal;
-        wx += lb[kLearnCorr * P];
-        wy += lb[(kLearnCorr + 1) * P];
-        wz += lb[(kLearnCorr + 2) * P];
-    }
-    if (a.kind == SF_FLOW_W_RAD_S || a.kind == SF_FLOW_W_FRAME) {
-        const float m = a.kind == SF_FLOW_W_RAD_S ? a.inv_dt : 1.0f;
-        out[o] = wx * m;
-        out[o + plane] = wy * m;
-        out[o + 2 * plane] = wz * m;
-        return;
-    }
-    const Geo g = pixel_geo(L, i, j);
-    if (a.kind == SF_FLOW_TANGENT_PX) {
-        out[o] = flow_u(g, wx, wy, wz);
-        out[o + plane] = flow_v(g, wx, wy, wz);
-    } else {   // normal: <eta, w> / dmu with dmu = sqrt(1 - eta_x^2) / (fx |r_n|)
-        const float q2 = sqrtf(fmaf(g.y, g.y, 1.0f)) * g.rinv;
-        out[o] = normal_s(g, wx, wy, wz) * g.fxrn / q2;
-    }
+    emit_flow(a, L, i, j, ldv((const T*)L.w[q][0], go) * fs, ldv((const T*)L.w[q][1], go) * fs,
+              ldv((const T*)L.w[q][2], go) * fs);
 }
 
 // ------------------------------------------------------------------------------------------
