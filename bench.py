@@ -110,8 +110,9 @@ def run_gpu(wl_name, steps, warmup, storage=0):
 
 def run_batched(n_streams, steps, warmup, storage=0, frames=6):
     """n_streams independent camera streams of mixed sizes advanced together: one pyramid
-    launch per depth, one level-step launch and one reconstruction launch per depth per
-    frame for all streams.  A step is one frame of every stream plus every stream's output."""
+    launch and one reconstruction launch per two depths, the level-step launches and one
+    output call per frame for all streams.  A step is one frame of every stream plus every
+    stream's output."""
     import torch
     from paper_2406_18031_amd import sflow
     from synth.workloads import stream_mix
@@ -138,8 +139,7 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
 
     def step(k):
         b.push([y[k % frames] for y in Ys], [r[k % frames] for r in Rs], dts)
-        for s_ in range(len(specs)):
-            sflow.sf_get_flow_stream(b.ctx, s_, sflow.SF_FLOW_W_RAD_S, outs[s_])
+        sflow.sf_get_flows(b.ctx, sflow.SF_FLOW_W_RAD_S, outs)
 
     # launch shape from the autotuner (pass length; tiles of the largest stream's levels)
     from paper_2406_18031_amd import tune
@@ -218,9 +218,13 @@ def run_learned(n_streams, steps, warmup, frames=6):
         if upd == sflow.SF_UPDATE_LEARNED:
             b.set_learned(learned.init_params(0), 1.0)
         dts = [dt] * n_streams
+        outs = [torch.empty((3, 512, 512), dtype=torch.float32, device="cuda")
+                for _ in range(n_streams)]
 
-        def step(k):
+        def step(k):   # a frame of every stream and every stream's output (the learned
+            # correction is applied to the output)
             b.push([y[k % frames] for y in Ys], [r[k % frames] for r in Rs], dts)
+            sflow.sf_get_flows(b.ctx, sflow.SF_FLOW_W_RAD_S, outs)
 
         for k in range(warmup):
             step(k)

@@ -174,6 +174,10 @@ sf_status sf_set_cameras(sf_ctx ctx, const sf_camera* cams);
 sf_status sf_push_frames(sf_ctx ctx, const void* const* Y, const void* const* rho,
                          const double* dt);
 sf_status sf_get_flow_stream(sf_ctx ctx, int32_t stream, int32_t kind, void* out);
+/* Every stream's output in one call: outs is a host array of n device pointers (NULL = skip
+ * that stream), each as out of sf_get_flow for that stream.  The results are bitwise those of
+ * sf_get_flow_stream; the streams' outputs are written by one or two launches. */
+sf_status sf_get_flows(sf_ctx ctx, int32_t kind, void* const* outs);
 sf_status sf_state_size_stream(sf_ctx ctx, int32_t stream, size_t* bytes);
 sf_status sf_get_state_stream(sf_ctx ctx, int32_t stream, void* host_blob, size_t bytes);
 /* on a batch of more than one stream, only after the first frame has been pushed */

@@ -884,6 +884,50 @@ sf_status sf_push_frame(sf_ctx c, const void* Y, const void* rho, double dt) {
     return sf_push_frames(c, &Y, &rho, &dt);
 }
 
+// Outputs of the streams s with outs[s] set.  With the finest reconstruction pending (and a
+// kind that depends on it) it runs now and writes the outputs of the streams it covers; the
+// others (single-level streams) get an output launch.
+static sf_status write_outputs(sf_ctx c, int32_t kind, float* const* outs) {
+    bool covered[kMaxStreams] = {};
+    if (kind != SF_FLOW_RHO && c->recon_pending) {
+        c->recon_pending = false;
+        ElemArgs r = tile_args(c, 0, 1, c->parity);
+        r.kind = kind;
+        for (int k = 0; k < r.n; ++k) {
+            const int s = c->lv[r.ent[k]].stream;
+            r.outs[k] = outs[s];
+            r.inv_dts[k] = (float)(1.0 / c->st[s].dt_prev);
+            covered[s] = true;
+        }
+        TimedLaunch t(c, 2);
+        HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
+        t.done();
+    }
+    ElemArgs a{};
+    a.lv = c->lv_dev;
+    a.parity = c->parity;
+    a.kind = kind;
+    int b = 0;
+    for (int s = 0; s < c->S; ++s) {
+        if (!outs[s] || covered[s]) continue;
+        const int e = c->st[s].e0;
+        a.ent[a.n] = e;
+        a.blk[a.n] = b;
+        a.outs[a.n] = outs[s];
+        a.inv_dts[a.n] = (float)(1.0 / c->st[s].dt_prev);
+        b += (c->lv[e].rows * c->lv[e].cols + kElemBlock - 1) / kElemBlock;
+        ++a.n;
+    }
+    a.blk[a.n] = b;
+    if (a.n > 0) HIP_TRY(c, launch_output(c->storage, a, c->stream));
+    return SF_OK;
+}
+
+static sf_status check_pushed(sf_ctx c) {
+    if (!c->camera || c->frames == 0) return fail(c, SF_ERR_STATE, "no frame has been pushed");
+    return SF_OK;
+}
+
 sf_status sf_get_flow_stream(sf_ctx c, int32_t stream, int32_t kind, void* out) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
@@ -891,37 +935,29 @@ sf_status sf_get_flow_stream(sf_ctx c, int32_t stream, int32_t kind, void* out) 
     if (kind < SF_FLOW_W_RAD_S || kind > SF_FLOW_W_FRAME)
         return fail(c, SF_ERR_INVALID_ARG, "unknown flow kind %d", kind);
     if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
-    if (!c->camera || c->frames == 0) return fail(c, SF_ERR_STATE, "no frame has been pushed");
-    const float inv_dt = (float)(1.0 / c->st[stream].dt_prev);
-    if (kind != SF_FLOW_RHO && c->recon_pending && c->st[stream].H >= 2) {
-        // the deferred reconstruction, writing this stream's output as it goes
-        c->recon_pending = false;
-        ElemArgs r = tile_args(c, 0, 1, c->parity);
-        r.kind = kind;
-        r.inv_dt = inv_dt;
-        r.out = (float*)out;
-        r.out_entry = c->st[stream].e0;
-        TimedLaunch t(c, 2);
-        HIP_TRY(c, launch_reconstruct(c->storage, r, c->stream));
-        t.done();
-        return SF_OK;
+    st = check_pushed(c);
+    if (st != SF_OK) return st;
+    float* outs[kMaxStreams] = {};
+    outs[stream] = (float*)out;
+    return write_outputs(c, kind, outs);
+}
+
+sf_status sf_get_flows(sf_ctx c, int32_t kind, void* const* outs) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!outs) return fail(c, SF_ERR_INVALID_ARG, "NULL output array");
+    if (kind < SF_FLOW_W_RAD_S || kind > SF_FLOW_W_FRAME)
+        return fail(c, SF_ERR_INVALID_ARG, "unknown flow kind %d", kind);
+    float* o[kMaxStreams] = {};
+    for (int s = 0; s < c->S; ++s) {
+        if (!outs[s]) continue;
+        if (!is_device_ptr(outs[s]))
+            return fail(c, SF_ERR_INVALID_ARG, "stream %d: out must be a device pointer", s);
+        o[s] = (float*)outs[s];
     }
-    if (kind != SF_FLOW_RHO) {   // the inverse depth does not depend on the reconstruction
-        st = flush_recon(c);
-        if (st != SF_OK) return st;
-    }
-    ElemArgs a{};
-    a.lv = c->lv_dev;
-    a.n = 1;
-    a.ent[0] = c->st[stream].e0;
-    a.blk[0] = 0;
-    a.blk[1] = (c->lv[a.ent[0]].rows * c->lv[a.ent[0]].cols + kElemBlock - 1) / kElemBlock;
-    a.parity = c->parity;
-    a.kind = kind;
-    a.inv_dt = inv_dt;
-    a.out = (float*)out;
-    HIP_TRY(c, launch_output(c->storage, a, c->stream));
-    return SF_OK;
+    st = check_pushed(c);
+    if (st != SF_OK) return st;
+    return write_outputs(c, kind, o);
 }
 
 sf_status sf_get_flow(sf_ctx c, int32_t kind, void* out) {

@@ -90,10 +90,11 @@ struct ElemArgs {
     int ent[kMaxStreams];
     int blk[kMaxStreams + 1];
     int parity;                      // state parity read/written by the kernel
-    int kind;                        // output kind (k_output)
-    float inv_dt;                    // output scale to rad/s (k_output)
-    float* out;                      // output planes (k_output; k_reconstruct when set)
-    int out_entry;                   // k_reconstruct: the finest-level entry whose output it writes
+    int kind;                        // output kind (k_output, k_reconstruct)
+    float* out;                      // output planes (k_learned_extract)
+    float* outs[kMaxStreams];        // k_output, k_reconstruct: output planes of the launch's
+                                     // k-th entry (NULL: none)
+    float inv_dts[kMaxStreams];      // their scale to rad/s
     FrameInputs in;
 };
 

@@ -649,9 +649,9 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
 }
 
 // The entry and pixel of a per-pixel launch; false past the entry's last pixel.
-__device__ __forceinline__ bool elem_pixel(const ElemArgs& a, int& e, int& i, int& j) {
+__device__ __forceinline__ bool elem_pixel(const ElemArgs& a, int& k, int& e, int& i, int& j) {
     const int b = blockIdx.x;
-    int k = 0;
+    k = 0;
     while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
     e = a.ent[k];
     const LevelDev& L = a.lv[e];
@@ -672,10 +672,10 @@ template <> __device__ __forceinline__ float rnd<__half>(float v) {
     return __half2float(__float2half(v));
 }
 
-// The entry and tile of a two-level tile launch.
-__device__ __forceinline__ int tile_entry(const ElemArgs& a, int& t) {
+// The entry (and its slot k in the launch) and tile of a two-level tile launch.
+__device__ __forceinline__ int tile_entry(const ElemArgs& a, int& k, int& t) {
     const int b = blockIdx.x;
-    int k = 0;
+    k = 0;
     while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
     t = b - a.blk[k];
     return a.ent[k];
@@ -720,8 +720,8 @@ template <typename T>
 __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     constexpr int P = kPyrPatch;
     __shared__ float pY[P][P + 1], pR[P][P + 1];
-    int t;
-    const LevelDev& D = a.lv[tile_entry(a, t)];
+    int k, t;
+    const LevelDev& D = a.lv[tile_entry(a, k, t)];
     const LevelDev& S = a.lv[D.child];
     const int ntx = (D.cols + kTile2 - 1) / kTile2;
     const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
@@ -780,8 +780,8 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
 // first frame: Yhat = G * Y, rho = measured (0 where missing), w = dw = 0, into state[0]
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
-    int e, i, j;
-    if (!elem_pixel(a, e, i, j)) return;
+    int k0, e, i, j;
+    if (!elem_pixel(a, k0, e, i, j)) return;
     const LevelDev& L = a.lv[e];
     const bool fin = L.level == 0;
     const T* Ym = (const T*)(fin ? a.in.Y[L.stream] : L.Ym);
@@ -811,10 +811,11 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
 }
 
 // One output pixel of a stream's finest level from its flow (rad/frame, as stored): the kind
-// a.kind into the planes a.out.  The learned update's correction is added here.
-__device__ __forceinline__ void emit_flow(const ElemArgs& a, const LevelDev& L, int i, int j,
-                                          float wx, float wy, float wz) {
-    float* out = a.out;
+// a.kind into the planes a.outs[k] of launch slot k.  The learned update's correction is added
+// here.
+__device__ __forceinline__ void emit_flow(const ElemArgs& a, int k, const LevelDev& L, int i,
+                                          int j, float wx, float wy, float wz) {
+    float* out = a.outs[k];
     const size_t plane = (size_t)L.rows * L.cols;
     const size_t o = (size_t)i * L.cols + j;
     if (L.learned) {   // the learned update's correction of the output
@@ -825,7 +826,7 @@ __device__ __forceinline__ void emit_flow(const ElemArgs& a, const LevelDev& L, 
         wz += lb[(kLearnCorr + 2) * P];
     }
     if (a.kind == SF_FLOW_W_RAD_S || a.kind == SF_FLOW_W_FRAME) {
-        const float m = a.kind == SF_FLOW_W_RAD_S ? a.inv_dt : 1.0f;
+        const float m = a.kind == SF_FLOW_W_RAD_S ? a.inv_dts[k] : 1.0f;
         out[o] = wx * m;
         out[o + plane] = wy * m;
         out[o + 2 * plane] = wz * m;
@@ -858,14 +859,14 @@ __device__ __forceinline__ float bilerp_up(Load W, int i, int j, int urows, int 
 // kTile2/2 + 1 per side) in LDS, as stored: reconstructed from U's parent when U is not the
 // top level (the block then also writes the U pixels (i, j) with (2i, 2j) in its tile, so
 // every U pixel is written once), read from the state otherwise.  Phase 2 reconstructs level h
-// and, for the entry a.out_entry when a.out is set, writes that stream's output (emit_flow),
+// and, for the launch slots whose a.outs is set, writes their stream's output (emit_flow),
 // bitwise what k_output would write after this launch.
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     constexpr int P = kTile2 / 2 + 1;
     __shared__ float pw[3][P][P + 1];
-    int t;
-    const int e = tile_entry(a, t);
+    int slot, t;
+    const int e = tile_entry(a, slot, t);
     const LevelDev& L = a.lv[e];
     const LevelDev& U = a.lv[L.parent];
     const int q = a.parity;
@@ -916,23 +917,23 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
         stv((T*)L.w[q][k], go, v * lout);
         w[k] = rnd<T>(v * lout) * lin;    // as k_output reads it back
     }
-    if (a.out && e == a.out_entry) emit_flow(a, L, i, j, w[0], w[1], w[2]);
+    if (a.outs[slot]) emit_flow(a, slot, L, i, j, w[0], w[1], w[2]);
 }
 
-// finest-level outputs of one stream (a single entry)
+// finest-level outputs of the streams of the launch (entries with a.outs set)
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
-    int e, i, j;
-    if (!elem_pixel(a, e, i, j)) return;
+    int k, e, i, j;
+    if (!elem_pixel(a, k, e, i, j)) return;
     const LevelDev& L = a.lv[e];
     const int q = a.parity;
     const size_t go = (size_t)i * L.pitch + j;
     if (a.kind == SF_FLOW_RHO) {
-        a.out[(size_t)i * L.cols + j] = ldv((const T*)L.rho[q], go);
+        a.outs[k][(size_t)i * L.cols + j] = ldv((const T*)L.rho[q], go);
         return;
     }
     const float fs = flow_in_scale<T>(L);
-    emit_flow(a, L, i, j, ldv((const T*)L.w[q][0], go) * fs, ldv((const T*)L.w[q][1], go) * fs,
+    emit_flow(a, k, L, i, j, ldv((const T*)L.w[q][0], go) * fs, ldv((const T*)L.w[q][1], go) * fs,
               ldv((const T*)L.w[q][2], go) * fs);
 }
 
@@ -1051,8 +1052,8 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
 // with a parent).
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
-    int e, i, j;
-    if (!elem_pixel(a, e, i, j)) return;
+    int k0, e, i, j;
+    if (!elem_pixel(a, k0, e, i, j)) return;
     const LevelDev& L = a.lv[e];
     const size_t npx = (size_t)L.rows * L.cols;
     const size_t o = (size_t)i * L.cols + j;

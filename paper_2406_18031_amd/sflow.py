@@ -88,6 +88,7 @@ def _load():
         "sf_push_frames": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                 ctypes.POINTER(ctypes.c_double)]),
         "sf_get_flow_stream": (st, [vp, ctypes.c_int32, ctypes.c_int32, vp]),
+        "sf_get_flows": (st, [vp, ctypes.c_int32, ctypes.POINTER(vp)]),
         "sf_state_size_stream": (st, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
         "sf_get_state_stream": (st, [vp, ctypes.c_int32, vp, ctypes.c_size_t]),
         "sf_set_state_stream": (st, [vp, ctypes.c_int32, vp, ctypes.c_size_t]),
@@ -116,7 +117,8 @@ lib = _load()
 EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_state_size",
             "sf_get_state", "sf_set_state", "sf_destroy", "sf_last_error", "sf_set_tile",
             "sf_set_timing", "sf_kernel_times", "sf_set_pass_steps", "sf_create_batch", "sf_stream_count",
-            "sf_set_cameras", "sf_push_frames", "sf_get_flow_stream", "sf_state_size_stream",
+            "sf_set_cameras", "sf_push_frames", "sf_get_flow_stream", "sf_get_flows",
+            "sf_state_size_stream",
             "sf_get_state_stream", "sf_set_state_stream", "sf_set_learned", "sf_learned_stats",
             "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
             "sf_net_forward", "sf_net_train_step", "sf_net_set_loss", "sf_net_destroy",
@@ -258,6 +260,14 @@ def sf_push_frames(ctx: int, Ys, rhos, dts) -> None:
 
 def sf_get_flow_stream(ctx: int, stream: int, kind: int, out) -> None:
     _check(lib.sf_get_flow_stream(ctx, stream, kind, _ptr(out)), ctx)
+
+
+def sf_get_flows(ctx: int, kind: int, outs) -> None:
+    """outs: one tensor (or None) per stream of the context."""
+    if len(outs) != sf_stream_count(ctx):
+        raise ValueError("sf_get_flows takes one output (or None) per stream")
+    arr = (ctypes.c_void_p * len(outs))(*[None if o is None else _ptr(o) for o in outs])
+    _check(lib.sf_get_flows(ctx, kind, arr), ctx)
 
 
 def sf_state_size_stream(ctx: int, stream: int) -> int:
@@ -514,6 +524,15 @@ class Batch:
                               device="cuda")
         sf_get_flow_stream(self.ctx, stream, kind, out)
         return out
+
+    def flows(self, kind=SF_FLOW_W_FRAME, outs=None):
+        """Every stream's output (sf_get_flows); outs: a list of tensors to fill, or None."""
+        import torch
+        if outs is None:
+            outs = [torch.empty((FLOW_COMPONENTS[kind], sp["rows"], sp["cols"]),
+                                dtype=torch.float32, device="cuda") for sp in self.specs]
+        sf_get_flows(self.ctx, kind, outs)
+        return outs
 
     def update_inputs(self, stream, out=None):
         import torch

@@ -139,3 +139,43 @@ def test_learned_correction_in_the_fused_output():
     assert px > 0 and fb < px
     a.close()
     b.close()
+
+
+def test_all_streams_in_one_call():
+    """sf_get_flows gives bitwise what sf_get_flow_stream gives, stream by stream."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    specs = [
+        dict(rows=72, cols=90, levels=3, max_flow_px=5.0, smooth=[2, 3, 1], camera=CAM),
+        dict(rows=40, cols=33, levels=1, max_flow_px=2.0, smooth=[2], camera=(40.0, 41.0, 16.0, 19.5)),
+        dict(rows=130, cols=64, levels=4, max_flow_px=9.0, smooth=[2, 4, 4, 4],
+             camera=(70.0, 70.0, 31.5, 64.5)),
+    ]
+    fr = [_frames(30 + s, 4, sp["rows"], sp["cols"]) for s, sp in enumerate(specs)]
+    a, b = sflow.Batch(specs), sflow.Batch(specs)
+    with pytest.raises(sflow.SflowError):
+        a.flows()                                   # nothing pushed yet
+    for k, kind in enumerate((0, 1, 2, 3)):
+        Ys = [fr[s][k][0] for s in range(len(specs))]
+        rhos = [fr[s][k][1] for s in range(len(specs))]
+        a.push(Ys, rhos, [0.01, 0.02, 0.005])
+        b.push(Ys, rhos, [0.01, 0.02, 0.005])
+        if k == 2:                                  # a subset: the others stay untouched
+            outs = [torch.full((sflow.FLOW_COMPONENTS[kind], sp["rows"], sp["cols"]), 7.0,
+                               device="cuda") for sp in specs]
+            a.flows(kind, [outs[0], None, outs[2]])
+            assert bool((outs[1] == 7.0).all())
+            got = [outs[0], a.flow(1, kind), outs[2]]
+        else:
+            got = a.flows(kind)
+        for s in range(len(specs)):
+            assert _same(got[s], b.flow(s, kind)), (k, s)
+    with pytest.raises(ValueError):
+        a.flows(0, [None])
+    host = np.zeros(3 * 72 * 90, np.float32)        # a host buffer is refused
+    with pytest.raises(sflow.SflowError):
+        sflow.sf_get_flows(a.ctx, 0, [host.ctypes.data, None, None])
+    with pytest.raises(sflow.SflowError):                # unknown kind
+        sflow.sf_get_flows(a.ctx, 9, a.flows(0))
+    a.close()
+    b.close()
