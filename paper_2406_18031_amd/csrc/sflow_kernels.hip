@@ -162,17 +162,18 @@ __device__ __forceinline__ void row_geo(const LevelDev& L, int i, float x, float
 constexpr int kNW = kBlock / 64;        // waves per block
 constexpr int kRPW = kRegion / kNW;     // region rows per wave
 
-// One column (beta_1) half-step of every valid row held by this wave.
+// One column (beta_1) half-step of every row held by this wave.  Rows outside the image or
+// outside the band still valid after the previous steps are stepped too (their values are
+// finite and reach only rows that leave the valid band themselves), so every field is updated
+// in place with no per-row branch.
 template <int NF, bool BORDER>
 __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&grinv)[kRPW],
                                             const float (&gfxrn)[kRPW], const float (&gxi)[kRPW],
-                                            const float (&gy)[kRPW], float x, int wi0, int ci0,
-                                            int ci1, bool at_left, bool at_right, float dt,
-                                            float fN, float dtsig, bool dom_lit, bool cfl) {
+                                            const float (&gy)[kRPW], float x, bool at_left,
+                                            bool at_right, float dt, float fN, float dtsig,
+                                            bool dom_lit, bool cfl) {
 #pragma unroll
     for (int r = 0; r < kRPW; ++r) {
-        const int i = wi0 + r;
-        if (i < ci0 || i >= ci1) continue;            // wave-uniform
         const float wx = F[r][0], wy = F[r][1], wz = F[r][2];
         const float t = fmaf(gy[r], wy, wz);
         const float u = gfxrn[r] * fmaf(-gxi[r], t, wx);      // b1.w / dmu
@@ -233,7 +234,6 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const bool left_b = border && at_left, right_b = border && at_right;
     // rows of the region held by this wave that lie in the image
     const int vi0 = max(gi0, 0), vi1 = min(gi0 + RH, R);
-    const int vj0 = max(gj0, 0), vj1 = min(gj0 + RW, C);
 
     // ---- geometry of this lane's pixels (pinhole closed forms, see pixel_geo) -------------
     const float x = fmaf((float)j, L.ifx, -L.cxn);
@@ -311,19 +311,16 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const float dtsig = dt * sig;
     const bool dom_lit = (L.flags & SF_READ_DOMINANT_LITERAL) != 0;
     const bool cfl = (L.flags & SF_READ_NO_CFL_CLAMP) == 0;
-    int ci0 = vi0, ci1 = vi1, cj0 = vj0, cj1 = vj1;
     float* XB = lds;   // [2][NW][2][NF][64] boundary rows of every wave, double-buffered
 
     for (int n = 0; n < L.pass_n; ++n) {   // the steps of this pass
         // column half-step: neighbours from adjacent lanes
         if (border)
-            column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, wi0, ci0, ci1, at_left, at_right,
-                                  dt, fN, dtsig, dom_lit, cfl);
+            column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, fN, dtsig,
+                                  dom_lit, cfl);
         else
-            column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, wi0, ci0, ci1, at_left, at_right,
-                                   dt, fN, dtsig, dom_lit, cfl);
-        cj0 = cj0 > 0 ? cj0 + 1 : cj0;
-        cj1 = cj1 < C ? cj1 - 1 : cj1;
+            column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, fN, dtsig,
+                                   dom_lit, cfl);
 
         // row half-step: neighbours from the rows above/below, across waves through LDS
         float* xb = XB + (n & 1) * (NW * 2 * NF * 64);
@@ -333,14 +330,15 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
             xb[((wave * 2 + 1) * NF + k) * 64 + lane] = F[RPW - 1][k];
         }
         __syncthreads();
+        // the first and last waves read a row of their own instead of the missing one: region
+        // edge rows are never valid after a step, only finite
         float above[NF], below[NF];
+        const int wa = wave > 0 ? wave - 1 : 0, wb = wave < NW - 1 ? wave + 1 : NW - 1;
 #pragma unroll
         for (int k = 0; k < NF; ++k) {
-            above[k] = wave > 0 ? xb[(((wave - 1) * 2 + 1) * NF + k) * 64 + lane] : 0.0f;
-            below[k] = wave < NW - 1 ? xb[(((wave + 1) * 2 + 0) * NF + k) * 64 + lane] : 0.0f;
+            above[k] = xb[((wa * 2 + 1) * NF + k) * 64 + lane];
+            below[k] = xb[((wb * 2 + 0) * NF + k) * 64 + lane];
         }
-        const int ni0 = ci0 > 0 ? ci0 + 1 : ci0;
-        const int ni1 = ci1 < R ? ci1 - 1 : ci1;
         float v[RPW];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) v[r] = gB[r] * fmaf(-gy[r], F[r][2], F[r][1]);
@@ -357,7 +355,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
 #pragma unroll
             for (int k = 0; k < NF; ++k) cur[k] = F[r][k];
             const float vc = v[r];
-            if (i >= ni0 && i < ni1) {                // wave-uniform
+            {
                 const bool top_b = i == 0, bot_b = i == R - 1;
                 const float vm = top_b ? vc : vprev;
                 const float vp = bot_b ? vc : (r + 1 < RPW ? v[r + 1 < RPW ? r + 1 : r] : vB);
@@ -384,8 +382,6 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
             for (int k = 0; k < NF; ++k) prev[k] = cur[k];
             vprev = vc;
         }
-        ci0 = ni0;
-        ci1 = ni1;
     }
     __syncthreads();   // the LDS below is reused for the update phase
 
