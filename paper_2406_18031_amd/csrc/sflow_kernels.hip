@@ -170,8 +170,8 @@ template <int NF, bool BORDER>
 __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&grinv)[kRPW],
                                             const float (&gfxrn)[kRPW], const float (&gxi)[kRPW],
                                             const float (&gy)[kRPW], float x, bool at_left,
-                                            bool at_right, float dt, float fN, float dtsig,
-                                            bool dom_lit, bool cfl) {
+                                            bool at_right, float dt, float lim, float dtsig,
+                                            bool dom_lit) {
 #pragma unroll
     for (int r = 0; r < kRPW; ++r) {
         const float wx = F[r][0], wy = F[r][1], wz = F[r][2];
@@ -181,13 +181,14 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
         const float up = nb_next<BORDER>(u, at_right);
         const bool larger_next = fabsf(up) > fabsf(um);
         float uh = dom_lit ? (larger_next ? um : up) : (larger_next ? up : um);
-        if (cfl) uh = __builtin_amdgcn_fmed3f(uh, -fN, fN);
+        uh = __builtin_amdgcn_fmed3f(uh, -lim, lim);         // stability bound (lim = N or inf)
         const float s = grinv[r] * fmaf(x, wx, t);           // <eta, w>
         // upwind step f - dt (u_hat D f + sigma s f) with D the one-sided difference toward
         // the upwind side, written as k0 f + ap f_left - am f_right with ap = dt max(u_hat, 0),
         // am = dt min(u_hat, 0), k0 = 1 - dt sigma s - ap + am (no source term for the image).
         // At the image border the missing neighbour equals the pixel itself, so its weight
-        // moves into k0, i.e. the coefficient is dropped.
+        // moves into k0, i.e. the coefficient is dropped.  The two neighbour products are
+        // plain multiplies so that the lane shifts fold into them (4 instructions per field).
         const float du = dt * uh;
         float ap = fmaxf(du, 0.0f), am = fminf(du, 0.0f);
         if (BORDER) {
@@ -311,16 +312,17 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const float dtsig = dt * sig;
     const bool dom_lit = (L.flags & SF_READ_DOMINANT_LITERAL) != 0;
     const bool cfl = (L.flags & SF_READ_NO_CFL_CLAMP) == 0;
+    const float lim = cfl ? fN : __builtin_inff();   // bound of the dominant flow
     float* XB = lds;   // [2][NW][2][NF][64] boundary rows of every wave, double-buffered
 
     for (int n = 0; n < L.pass_n; ++n) {   // the steps of this pass
         // column half-step: neighbours from adjacent lanes
         if (border)
-            column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, fN, dtsig,
-                                  dom_lit, cfl);
+            column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, lim, dtsig,
+                                  dom_lit);
         else
-            column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, fN, dtsig,
-                                   dom_lit, cfl);
+            column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, lim, dtsig,
+                                   dom_lit);
 
         // row half-step: neighbours from the rows above/below, across waves through LDS
         float* xb = XB + (n & 1) * (NW * 2 * NF * 64);
@@ -361,7 +363,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
                 const float vp = bot_b ? vc : (r + 1 < RPW ? v[r + 1 < RPW ? r + 1 : r] : vB);
                 const bool larger_next = fabsf(vp) > fabsf(vm);
                 float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
-                if (cfl) vh = __builtin_amdgcn_fmed3f(vh, -fN, fN);
+                vh = __builtin_amdgcn_fmed3f(vh, -lim, lim);
                 const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
                 // same upwind form as the column pass, neighbours above and below
                 const float dv = dt * vh;
