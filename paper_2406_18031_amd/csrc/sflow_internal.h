@@ -13,9 +13,10 @@ constexpr int kMaxLevels = SF_MAX_LEVELS;
 constexpr int kBlock = 1024;         // threads per block of the fused level kernel
 constexpr int kRegion = 64;          // max rows/columns of a tile plus its halo
 // LDS of the fused level kernel: the larger of the row-pass exchange buffers
-// (2 buffers x waves x 2 rows x 8 fields x 64 lanes) and the update planes (5 x 64 x 64)
+// (2 buffers x waves x 2 rows x 8 fields x 64 lanes) and the update planes (8 x 64 x 64: the
+// image model's 2, the smoothing's 2 x 3)
 constexpr size_t kLdsXB = 2 * (kBlock / 64) * 2 * 8 * 64 * sizeof(float);
-constexpr size_t kLdsPlanes = 5 * kRegion * 64 * sizeof(float);
+constexpr size_t kLdsPlanes = 8 * kRegion * 64 * sizeof(float);
 constexpr size_t kLdsBytes = kLdsXB > kLdsPlanes ? kLdsXB : kLdsPlanes;
 
 constexpr int kMaxStreams = 64;

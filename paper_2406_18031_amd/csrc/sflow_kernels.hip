@@ -209,6 +209,86 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
     }
 }
 
+// Sum of the 5 column neighbours j-2..j+2 of a row held across the wave's lanes; at the image's
+// left/right border the border pixel repeats.  BORDER is false for regions that touch neither.
+template <bool BORDER>
+__device__ __forceinline__ float hsum5(float v0, bool left_b, bool right_b) {
+    float m1, m2, p1, p2;
+    if (BORDER) {
+        m1 = clamp_prev(v0, left_b);
+        m2 = clamp_prev(m1, left_b);
+        p1 = clamp_next(v0, right_b);
+        p2 = clamp_next(p1, right_b);
+    } else {
+        m1 = dpp_prev(v0);
+        m2 = dpp_prev(m1);
+        p1 = dpp_next(v0);
+        p2 = dpp_next(p1);
+    }
+    return (((m2 + m1) + v0) + p1) + p2;
+}
+
+// N_s passes of the 5x5 average (1/25) of fields KX..KX+2, every row of the wave's strip (rows
+// outside the band that is still valid stay finite and reach only rows that leave the band).
+// A pass: horizontal sums by lane shifts, written to an LDS plane; after one barrier the
+// vertical sums take the strip's own rows from registers and the two rows above and below it
+// from the plane, unless the strip lies within 2 rows of the image's top or bottom, where all
+// five rows are read from the plane at clamped image rows.  The planes (LDS planes 2-4 and
+// 5-7, clear of the image-model planes 0-1 still read by slower waves) alternate between
+// passes, so one barrier per pass suffices.
+template <int NF, int KX, bool BORDER>
+__device__ __forceinline__ void smooth_passes(float (&F)[kRPW][NF], float* lds, int Ns, int wave,
+                                              int lane, int wi0, int gi0, int R, bool left_b,
+                                              bool right_b) {
+    constexpr int RPW = kRPW;
+    const bool inner = wi0 - 2 >= 0 && wi0 + RPW + 2 <= R;    // wave-uniform
+    for (int sp = 0; sp < Ns; ++sp) {
+        float* PT = lds + (2 + 3 * (sp & 1)) * (kRegion * 64);   // [3][64 rows][64 lanes]
+        float hs[RPW][3];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int row = wave * RPW + r;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                hs[r][k] = hsum5<BORDER>(F[r][KX + k], left_b, right_b);
+                PT[(k * kRegion + row) * 64 + lane] = hs[r][k];
+            }
+        }
+        __syncthreads();
+        if (inner) {
+            const int ra = max(wave * RPW - 2, 0), rb = min(wave * RPW + RPW, kRegion - 2);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float h[RPW + 4];
+                h[0] = PT[(k * kRegion + ra) * 64 + lane];
+                h[1] = PT[(k * kRegion + ra + 1) * 64 + lane];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) h[r + 2] = hs[r][k];
+                h[RPW + 2] = PT[(k * kRegion + rb) * 64 + lane];
+                h[RPW + 3] = PT[(k * kRegion + rb + 1) * 64 + lane];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r)
+                    F[r][KX + k] = ((((h[r] + h[r + 1]) + h[r + 2]) + h[r + 3]) + h[r + 4]) * 0.04f;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const int i = wi0 + r;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float t = 0.0f;
+#pragma unroll
+                    for (int aa = -2; aa <= 2; ++aa) {
+                        const int rr = clampi(clampi(i + aa, 0, R - 1) - gi0, 0, kRegion - 1);
+                        t += PT[(k * kRegion + rr) * 64 + lane];
+                    }
+                    F[r][KX + k] = t * 0.04f;
+                }
+            }
+        }
+    }
+}
+
 template <typename T, bool TOP>
 __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L, int h, int t,
                                            float* lds) {
@@ -407,7 +487,6 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     const int mi0 = max(si0 - 2, 0), mi1 = min(si1 + 2, R);
     float* PHG = lds;                    // [64 rows][64 lanes]
     float* PHD = lds + kRegion * 64;
-    float* PT = lds + 2 * kRegion * 64;  // [3][64][64] smoothing
 
     // horizontal taps of the image model in registers
 #pragma unroll
@@ -560,41 +639,10 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
 
     // ---- smoothing: N_s passes of the 5x5 average ---------------------------------------------
     constexpr int KX = TOP ? 0 : 3;
-    for (int sp = 1; sp <= Ns; ++sp) {
-        const int rad = 2 * (Ns - sp);
-        const int oi0 = max(ti0 - rad, 0), oi1 = min(ti1 + rad, R);
-        const int ii0 = max(oi0 - 2, 0), ii1 = min(oi1 + 2, R);
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int i = wi0 + r;
-            if (i < ii0 || i >= ii1) continue;        // wave-uniform
-            const int row = wave * RPW + r;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float v0 = F[r][KX + k];
-                const float m1 = clamp_prev(v0, left_b);
-                const float m2 = clamp_prev(m1, left_b);
-                const float p1 = clamp_next(v0, right_b);
-                const float p2 = clamp_next(p1, right_b);
-                PT[(k * kRegion + row) * 64 + lane] = (((m2 + m1) + v0) + p1) + p2;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int i = wi0 + r;
-            if (i < oi0 || i >= oi1) continue;        // wave-uniform
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                float s = 0.0f;
-#pragma unroll
-                for (int aa = -2; aa <= 2; ++aa)
-                    s += PT[(k * kRegion + (clampi(i + aa, 0, R - 1) - gi0)) * 64 + lane];
-                F[r][KX + k] = s * 0.04f;
-            }
-        }
-        __syncthreads();
-    }
+    if (border)
+        smooth_passes<NF, KX, true>(F, lds, Ns, wave, lane, wi0, gi0, R, left_b, right_b);
+    else
+        smooth_passes<NF, KX, false>(F, lds, Ns, wave, lane, wi0, gi0, R, left_b, right_b);
 
     // ---- store the solved field of the tile -----------------------------------------------
     {
