@@ -196,8 +196,11 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
             am = at_right ? 0.0f : am;
         }
         const float c = fmaf(-dtsig, s, 1.0f);
-        const float k0 = (c - ap) + am;
-        const float k1 = (1.0f - ap) + am;
+        // one of ap, am is 0, so c - (ap - am) = (c - ap) + am exactly; ap - am = |du| unless
+        // a coefficient was dropped at the border
+        const float d = BORDER ? ap - am : fabsf(du);
+        const float k0 = c - d;
+        const float k1 = 1.0f - d;
 #pragma unroll
         for (int k = 0; k < NF; ++k) {
             const float f = F[r][k];
@@ -206,6 +209,61 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
             const float kk = (NF == 8 && k == 7) ? k1 : k0;
             F[r][k] = fmaf(kk, f, fm * ap - fp * am);
         }
+    }
+}
+
+// One row (beta_2) half-step of every row held by this wave: row neighbours from the wave's
+// own registers and, for its first and last rows, the rows above and below the strip (from
+// the neighbouring waves).  Same upwind form as the column pass; at the image's first and last
+// row the missing neighbour's coefficient is dropped.
+template <int NF, bool TOP>
+__device__ __forceinline__ void row_pass(float (&F)[kRPW][NF], const float (&above)[NF],
+                                         const float (&below)[NF], const float (&grinv)[kRPW],
+                                         const float (&gy)[kRPW], const float (&gB)[kRPW],
+                                         float x, float yA, float BA, float yBl, float BBl,
+                                         int wi0, int R, float dt, float lim, float dtsig,
+                                         bool dom_lit) {
+    constexpr int RPW = kRPW;
+    float v[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) v[r] = gB[r] * fmaf(-gy[r], F[r][2], F[r][1]);
+    const float vA = BA * fmaf(-yA, above[2], above[1]);
+    const float vB = BBl * fmaf(-yBl, below[2], below[1]);
+    float prev[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) prev[k] = above[k];
+    float vprev = vA;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int i = wi0 + r;
+        float cur[NF];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) cur[k] = F[r][k];
+        const float vc = v[r];
+        const bool top_b = i == 0, bot_b = i == R - 1;
+        const float vm = top_b ? vc : vprev;
+        const float vp = bot_b ? vc : (r + 1 < RPW ? v[r + 1 < RPW ? r + 1 : r] : vB);
+        const bool larger_next = fabsf(vp) > fabsf(vm);
+        float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
+        vh = __builtin_amdgcn_fmed3f(vh, -lim, lim);
+        const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
+        const float dv = dt * vh;
+        const float ap = top_b ? 0.0f : fmaxf(dv, 0.0f);
+        const float am = bot_b ? 0.0f : fminf(dv, 0.0f);
+        const float c = fmaf(-dtsig, s, 1.0f);
+        const float d = ap - am;          // one of ap, am is 0: c - d = (c - ap) + am exactly
+        const float k0 = c - d;
+        const float k1 = 1.0f - d;
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const float fm = prev[k];
+            const float fp = r + 1 < RPW ? F[r + 1 < RPW ? r + 1 : r][k] : below[k];
+            const float kk = (!TOP && k == 7) ? k1 : k0;
+            F[r][k] = fmaf(-am, fp, fmaf(ap, fm, kk * cur[k]));
+        }
+#pragma unroll
+        for (int k = 0; k < NF; ++k) prev[k] = cur[k];
+        vprev = vc;
     }
 }
 
@@ -403,7 +461,6 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
         else
             column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, lim, dtsig,
                                    dom_lit);
-
         // row half-step: neighbours from the rows above/below, across waves through LDS
         float* xb = XB + (n & 1) * (NW * 2 * NF * 64);
 #pragma unroll
@@ -421,49 +478,8 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
             above[k] = xb[((wa * 2 + 1) * NF + k) * 64 + lane];
             below[k] = xb[((wb * 2 + 0) * NF + k) * 64 + lane];
         }
-        float v[RPW];
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) v[r] = gB[r] * fmaf(-gy[r], F[r][2], F[r][1]);
-        const float vA = BA * fmaf(-yA, above[2], above[1]);
-        const float vB = BBl * fmaf(-yBl, below[2], below[1]);
-        float prev[NF];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) prev[k] = above[k];
-        float vprev = vA;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int i = wi0 + r;
-            float cur[NF];
-#pragma unroll
-            for (int k = 0; k < NF; ++k) cur[k] = F[r][k];
-            const float vc = v[r];
-            {
-                const bool top_b = i == 0, bot_b = i == R - 1;
-                const float vm = top_b ? vc : vprev;
-                const float vp = bot_b ? vc : (r + 1 < RPW ? v[r + 1 < RPW ? r + 1 : r] : vB);
-                const bool larger_next = fabsf(vp) > fabsf(vm);
-                float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
-                vh = __builtin_amdgcn_fmed3f(vh, -lim, lim);
-                const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
-                // same upwind form as the column pass, neighbours above and below
-                const float dv = dt * vh;
-                const float ap = top_b ? 0.0f : fmaxf(dv, 0.0f);
-                const float am = bot_b ? 0.0f : fminf(dv, 0.0f);
-                const float c = fmaf(-dtsig, s, 1.0f);
-                const float k0 = (c - ap) + am;
-                const float k1 = (1.0f - ap) + am;
-#pragma unroll
-                for (int k = 0; k < NF; ++k) {
-                    const float fm = prev[k];
-                    const float fp = r + 1 < RPW ? F[r + 1 < RPW ? r + 1 : r][k] : below[k];
-                    const float kk = (!TOP && k == 7) ? k1 : k0;
-                    F[r][k] = fmaf(-am, fp, fmaf(ap, fm, kk * cur[k]));
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < NF; ++k) prev[k] = cur[k];
-            vprev = vc;
-        }
+        row_pass<NF, TOP>(F, above, below, grinv, gy, gB, x, yA, BA, yBl, BBl, wi0, R, dt, lim,
+                          dtsig, dom_lit);
     }
     __syncthreads();   // the LDS below is reused for the update phase
 
