@@ -27,14 +27,25 @@ __device__ __forceinline__ float ldv(const __half* p, size_t i) { return __half2
 __device__ __forceinline__ void stv(float* p, size_t i, float v) { p[i] = v; }
 __device__ __forceinline__ void stv(__half* p, size_t i, float v) { p[i] = __float2half(v); }
 
-template <typename T> __device__ __forceinline__ float flow_in_scale(const LevelDev& L);
-template <> __device__ __forceinline__ float flow_in_scale<float>(const LevelDev&) { return 1.0f; }
-template <> __device__ __forceinline__ float flow_in_scale<__half>(const LevelDev& L) {
+// The level table is written by the host before a launch and never by a kernel, so kernels
+// read it through the constant address space: the compiler may then use scalar loads for it
+// (uniform, cached, issued early) instead of vector loads ordered behind the kernel's stores.
+typedef const __attribute__((address_space(4))) LevelDev ConstLevelDev;
+__device__ __forceinline__ ConstLevelDev& level_entry(const LevelDev* tab, int e) {
+    return ((ConstLevelDev*)tab)[e];
+}
+__device__ __forceinline__ int level_block0(const LevelDev* tab, int e) {
+    return ((ConstLevelDev*)tab)[e].block0;
+}
+
+template <typename T> __device__ __forceinline__ float flow_in_scale(ConstLevelDev& L);
+template <> __device__ __forceinline__ float flow_in_scale<float>(ConstLevelDev&) { return 1.0f; }
+template <> __device__ __forceinline__ float flow_in_scale<__half>(ConstLevelDev& L) {
     return 1.0f / L.qscale;
 }
-template <typename T> __device__ __forceinline__ float flow_out_scale(const LevelDev& L);
-template <> __device__ __forceinline__ float flow_out_scale<float>(const LevelDev&) { return 1.0f; }
-template <> __device__ __forceinline__ float flow_out_scale<__half>(const LevelDev& L) {
+template <typename T> __device__ __forceinline__ float flow_out_scale(ConstLevelDev& L);
+template <> __device__ __forceinline__ float flow_out_scale<float>(ConstLevelDev&) { return 1.0f; }
+template <> __device__ __forceinline__ float flow_out_scale<__half>(ConstLevelDev& L) {
     return L.qscale;
 }
 
@@ -58,7 +69,7 @@ struct Geo {
     float x, y, rinv, r, fxrn, inv1py2;
 };
 
-__device__ __forceinline__ Geo pixel_geo(const LevelDev& L, int i, int j) {
+__device__ __forceinline__ Geo pixel_geo(ConstLevelDev& L, int i, int j) {
     Geo g;
     g.x = fmaf((float)j, L.ifx, -L.cxn);
     g.y = fmaf((float)i, L.ify, -L.cyn);
@@ -73,7 +84,7 @@ __device__ __forceinline__ Geo pixel_geo(const LevelDev& L, int i, int j) {
 }
 
 // dmu = sqrt(1 - eta_x^2) / (fx |r_n|), computed as in the update stage of k_step
-__device__ __forceinline__ float pixel_dmu(const LevelDev& L, int i, int j) {
+__device__ __forceinline__ float pixel_dmu(ConstLevelDev& L, int i, int j) {
     const float x = fmaf((float)j, L.ifx, -L.cxn);
     const float xn = x + (j < L.cols - 1 ? L.ifx : -L.ifx);
     const float y = fmaf((float)i, L.ify, -L.cyn);
@@ -147,7 +158,7 @@ __device__ __forceinline__ float clamp_next(float v, bool keep) {
 
 // Geometry of pixel (i, j) for the register-strip kernel: y, 1/|r|, fx |r_n|, x/(1 + y^2)
 // and B = fx |r_n| |r| / (1 + y^2) (see pixel_geo for the closed forms).
-__device__ __forceinline__ void row_geo(const LevelDev& L, int i, float x, float xn, float& y,
+__device__ __forceinline__ void row_geo(ConstLevelDev& L, int i, float x, float xn, float& y,
                                         float& rinv, float& fxrn, float& xi, float& B) {
     y = fmaf((float)i, L.ify, -L.cyn);
     const float yy1 = fmaf(y, y, 1.0f);
@@ -348,7 +359,7 @@ __device__ __forceinline__ void smooth_passes(float (&F)[kRPW][NF], float* lds, 
 }
 
 template <typename T, bool TOP>
-__device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L, int h, int t,
+__device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, int h, int t,
                                            float* lds) {
     constexpr int NF = TOP ? 4 : 8;   // top: w(3), rho; lower: w(3), dw(3), rho, Yhat
     constexpr int NW = kNW;
@@ -391,55 +402,69 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, const LevelDev& L,
     }
 
     // ---- load the frame-k state of the region into registers ------------------------------
+    // Every load is issued unconditionally, from an address clamped into the plane (pixel 0 for
+    // lanes and rows outside the image), so that all of them are in flight together; those
+    // lanes and rows are zeroed afterwards.
     float F[RPW][NF];
+    bool rok[RPW];
+    size_t gof[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int i = wi0 + r;
+        rok[r] = lane_ok && i >= vi0 && i < vi1;
+        gof[r] = rok[r] ? (size_t)i * L.pitch + j : 0;
+    }
     if (!L.pass_first) {    // a later pass of a split prediction: the fields after the last one
 #pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int i = wi0 + r;
-            const bool ok = lane_ok && i >= vi0 && i < vi1;
-            const size_t g = (size_t)(ok ? i : 0) * L.pitch + (ok ? j : 0);
+        for (int r = 0; r < RPW; ++r)
 #pragma unroll
-            for (int k = 0; k < NF; ++k) F[r][k] = ok ? L.mid_in[k][g] : 0.0f;
-        }
+            for (int k = 0; k < NF; ++k) F[r][k] = L.mid_in[k][gof[r]];
     } else {
         const float fs = flow_in_scale<T>(L) * a.in.scale[L.stream];
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
-            const int i = wi0 + r;
-            const bool ok = lane_ok && i >= vi0 && i < vi1;
-            const size_t g = (size_t)(ok ? i : 0) * L.pitch + (ok ? j : 0);
+            const size_t g = gof[r];
 #pragma unroll
-            for (int k = 0; k < NF; ++k) F[r][k] = 0.0f;
-            if (ok) {
+            for (int k = 0; k < 3; ++k) F[r][k] = ldv((const T*)L.w[par][k], g) * fs;
+            F[r][KR] = ldv((const T*)L.rho[par], g);
+            if constexpr (!TOP) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) F[r][k] = ldv((const T*)L.w[par][k], g) * fs;
-                F[r][KR] = ldv((const T*)L.rho[par], g);
-                if constexpr (!TOP) {
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) F[r][3 + k] = ldv((const T*)L.dw[par][k], g) * fs;
-                    F[r][7] = ldv((const T*)L.Y[par], g);
-                }
+                for (int k = 0; k < 3; ++k) F[r][3 + k] = ldv((const T*)L.dw[par][k], g) * fs;
+                F[r][7] = ldv((const T*)L.Y[par], g);
             }
         }
     }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int k = 0; k < NF; ++k) F[r][k] = rok[r] ? F[r][k] : 0.0f;
 
     // ---- measurements of the update, loaded now so that their latency hides behind the
     // prediction: the new image at this wave's rows, the inverse depth at its rows and the rows
-    // just above and below (clamped to the image) ---------------------------------------------
+    // just above and below (clamped to the image; lanes outside it read column 0 and are
+    // zeroed) -------------------------------------------------------------------------------
     const T* Ymeas = (const T*)(h == 0 ? a.in.Y[L.stream] : L.Ym);
     const T* Rmeas = (const T*)(h == 0 ? a.in.R[L.stream] : L.Rm);
     const int mp = h == 0 ? C : L.pitch;
     float ypre[RPW], rpre[RPW + 2];
-    const bool meas = lane_ok && L.pass_last;
+    if (L.pass_last) {
+        const int jc = lane_ok ? j : 0;
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        const int i = wi0 + r;
-        ypre[r] = (meas && i >= 0 && i < R) ? ldv(Ymeas, (size_t)i * mp + j) : 0.0f;
-    }
+        for (int r = 0; r < RPW; ++r) {
+            const int i = wi0 + r;
+            const float y = ldv(Ymeas, (size_t)clampi(i, 0, R - 1) * mp + jc);
+            ypre[r] = (lane_ok && i >= 0 && i < R) ? y : 0.0f;
+        }
 #pragma unroll
-    for (int t = 0; t < RPW + 2; ++t) {
-        const int i = clampi(wi0 - 1 + t, 0, R - 1);
-        rpre[t] = meas ? ldv(Rmeas, (size_t)i * mp + j) : 0.0f;
+        for (int t = 0; t < RPW + 2; ++t) {
+            const float rv = ldv(Rmeas, (size_t)clampi(wi0 - 1 + t, 0, R - 1) * mp + jc);
+            rpre[t] = lane_ok ? rv : 0.0f;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) ypre[r] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < RPW + 2; ++t) rpre[t] = 0.0f;
     }
 
     // ---- prediction -------------------------------------------------------------------------
@@ -701,9 +726,9 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     int lo = 0, hi = a.nent - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (a.lv[mid].block0 <= b) lo = mid; else hi = mid - 1;
+        if (level_block0(a.lv, mid) <= b) lo = mid; else hi = mid - 1;
     }
-    const LevelDev& L = a.lv[lo];
+    ConstLevelDev& L = level_entry(a.lv, lo);
     if (L.top)
         level_tile<T, true>(a, L, L.level, b - L.block0, lds);
     else
@@ -716,7 +741,7 @@ __device__ __forceinline__ bool elem_pixel(const ElemArgs& a, int& k, int& e, in
     k = 0;
     while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
     e = a.ent[k];
-    const LevelDev& L = a.lv[e];
+    ConstLevelDev& L = level_entry(a.lv, e);
     const int p = (b - a.blk[k]) * kElemBlock + threadIdx.x;
     if (p >= L.rows * L.cols) return false;
     i = p / L.cols;
@@ -783,15 +808,15 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     constexpr int P = kPyrPatch;
     __shared__ float pY[P][P + 1], pR[P][P + 1];
     int k, t;
-    const LevelDev& D = a.lv[tile_entry(a, k, t)];
-    const LevelDev& S = a.lv[D.child];
+    ConstLevelDev& D = level_entry(a.lv, tile_entry(a, k, t));
+    ConstLevelDev& S = level_entry(a.lv, D.child);
     const int ntx = (D.cols + kTile2 - 1) / kTile2;
     const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
     const bool two = D.parent >= 0;
     int r0 = ti0, r1 = min(ti0 + kTile2, D.rows), q0 = tj0, q1 = min(tj0 + kTile2, D.cols);
     int a2 = 0, b2 = 0, c2 = 0, d2 = 0;
     if (two) {
-        const LevelDev& U = a.lv[D.parent];
+        ConstLevelDev& U = level_entry(a.lv, D.parent);
         a2 = ti0 / 2;
         b2 = min(a2 + kTile2 / 2, U.rows);
         c2 = tj0 / 2;
@@ -826,7 +851,7 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     }
     if (!two) return;
     __syncthreads();
-    const LevelDev& U = a.lv[D.parent];
+    ConstLevelDev& U = level_entry(a.lv, D.parent);
     const int i = a2 + p / (kTile2 / 2), j = c2 + p % (kTile2 / 2);
     if (p >= (kTile2 / 2) * (kTile2 / 2) || i >= b2 || j >= d2) return;
     auto from_lds = [&](int ii, int jj, float& y, float& r) {
@@ -844,7 +869,7 @@ template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
     int k0, e, i, j;
     if (!elem_pixel(a, k0, e, i, j)) return;
-    const LevelDev& L = a.lv[e];
+    ConstLevelDev& L = level_entry(a.lv, e);
     const bool fin = L.level == 0;
     const T* Ym = (const T*)(fin ? a.in.Y[L.stream] : L.Ym);
     const T* Rm = (const T*)(fin ? a.in.R[L.stream] : L.Rm);
@@ -875,7 +900,7 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
 // One output pixel of a stream's finest level from its flow (rad/frame, as stored): the kind
 // a.kind into the planes a.outs[k] of launch slot k.  The learned update's correction is added
 // here.
-__device__ __forceinline__ void emit_flow(const ElemArgs& a, int k, const LevelDev& L, int i,
+__device__ __forceinline__ void emit_flow(const ElemArgs& a, int k, ConstLevelDev& L, int i,
                                           int j, float wx, float wy, float wz) {
     float* out = a.outs[k];
     const size_t plane = (size_t)L.rows * L.cols;
@@ -929,8 +954,8 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     __shared__ float pw[3][P][P + 1];
     int slot, t;
     const int e = tile_entry(a, slot, t);
-    const LevelDev& L = a.lv[e];
-    const LevelDev& U = a.lv[L.parent];
+    ConstLevelDev& L = level_entry(a.lv, e);
+    ConstLevelDev& U = level_entry(a.lv, L.parent);
     const int q = a.parity;
     const int ntx = (L.cols + kTile2 - 1) / kTile2;
     const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
@@ -952,7 +977,7 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
         if (U.top) {
             for (int k = 0; k < 3; ++k) pw[k][ui - pa][uj - pc] = ldv((const T*)U.w[q][k], uo);
         } else {
-            const LevelDev& V = a.lv[U.parent];
+            ConstLevelDev& V = level_entry(a.lv, U.parent);
             const float vin = flow_in_scale<T>(V), uin = flow_in_scale<T>(U);
             const float uout = flow_out_scale<T>(U);
             const bool wr = 2 * ui >= ti0 && 2 * ui < ti1 && 2 * uj >= tj0 && 2 * uj < tj1;
@@ -987,7 +1012,7 @@ template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
     int k, e, i, j;
     if (!elem_pixel(a, k, e, i, j)) return;
-    const LevelDev& L = a.lv[e];
+    ConstLevelDev& L = level_entry(a.lv, e);
     const int q = a.parity;
     const size_t go = (size_t)i * L.pitch + j;
     if (a.kind == SF_FLOW_RHO) {
@@ -1018,7 +1043,7 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
     const int b = blockIdx.x;
     int k = 0;
     while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
-    const LevelDev& L = a.lv[a.ent[k]];
+    ConstLevelDev& L = level_entry(a.lv, a.ent[k]);
     const int R = L.rows, C = L.cols;
     const int t = b - a.blk[k];
     const int tilesx = (C + kCombTile - 1) / kCombTile;
@@ -1116,7 +1141,7 @@ template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     int k0, e, i, j;
     if (!elem_pixel(a, k0, e, i, j)) return;
-    const LevelDev& L = a.lv[e];
+    ConstLevelDev& L = level_entry(a.lv, e);
     const size_t npx = (size_t)L.rows * L.cols;
     const size_t o = (size_t)i * L.cols + j;
     const size_t P = (size_t)L.ltotal;
@@ -1125,7 +1150,7 @@ __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     for (int k = 0; k < 3; ++k) a.out[(kLearnFB + k) * npx + o] = lb[(kLearnXS + k) * P];
     float base[3] = {0.0f, 0.0f, 0.0f};
     if (!L.top) {
-        const LevelDev& U = a.lv[L.parent];
+        ConstLevelDev& U = level_entry(a.lv, L.parent);
         const int q = a.parity;
         const int i0 = i >> 1, j0 = j >> 1;
         const int i1 = min(i0 + 1, U.rows - 1), j1 = min(j0 + 1, U.cols - 1);
