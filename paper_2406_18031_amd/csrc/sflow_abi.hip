@@ -370,7 +370,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
             q = (q + 1) / 2;
         }
     }
-    total += align + sizeof(LevelDev) * ctx->lv.size();
+    total += align + sizeof(LevelDev) * (ctx->lv.size() + kLevelPad);   // zeroed padding
     hipError_t e = hipMalloc((void**)&ctx->arena, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -392,7 +392,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         L.Ym = L.level > 0 ? take(pb) : nullptr;
         L.Rm = L.level > 0 ? take(pb) : nullptr;
     }
-    ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * ctx->lv.size());
+    ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * (ctx->lv.size() + kLevelPad));
     if (cf[0].update == SF_UPDATE_LEARNED) {
         ctx->learned = true;
         CnnSegs& sg = ctx->segs;

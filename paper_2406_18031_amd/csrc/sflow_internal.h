@@ -19,8 +19,9 @@ constexpr size_t kLdsXB = 2 * (kBlock / 64) * 2 * 8 * 64 * sizeof(float);
 constexpr size_t kLdsPlanes = 8 * kRegion * 64 * sizeof(float);
 constexpr size_t kLdsBytes = kLdsXB > kLdsPlanes ? kLdsXB : kLdsPlanes;
 
-constexpr int kMaxStreams = 64;
-constexpr int kDefaultPassSteps = 8;   // prediction steps per step launch before a level splits      // camera streams per context
+constexpr int kMaxStreams = 64;        // camera streams per context
+constexpr int kLevelPad = 2;           // zeroed entries after the device level table
+constexpr int kDefaultPassSteps = 8;   // prediction steps per step launch before a level splits
 // Planes of the learned-update buffers of a finest level: network inputs (6), prior x0 (3),
 // least-squares solution (3), cost terms a_Y (3), a_rho (3), G1, G2 (2) and the network's
 // output (3), each `ltotal` floats.
@@ -35,7 +36,9 @@ static_assert(kTile2 * kTile2 == kElemBlock, "one thread per tile pixel");
 
 // Parameters of one pyramid level of one camera stream ("entry"), uploaded to device memory
 // whenever the camera or the tiling changes.  Entries are ordered stream by stream, finest
-// level first.
+// level first, so a level's finer and coarser neighbours are entries e - 1 and e + 1.  The
+// device table is followed by kLevelPad zeroed entries: kernels read entries e + 1 and e + 2
+// before knowing whether they belong to the same stream.
 struct LevelDev {
     int rows, cols, pitch;           // level size; row pitch (elements) of state/pyramid planes
     float ifx, ify, cxn, cyn;        // x = j*ifx - cxn, y = i*ify - cyn (pinhole ray)

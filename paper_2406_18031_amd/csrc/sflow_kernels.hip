@@ -808,19 +808,26 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     constexpr int P = kPyrPatch;
     __shared__ float pY[P][P + 1], pR[P][P + 1];
     int k, t;
-    ConstLevelDev& D = level_entry(a.lv, tile_entry(a, k, t));
-    ConstLevelDev& S = level_entry(a.lv, D.child);
+    const int e = tile_entry(a, k, t);
+    // a stream's entries are consecutive, finest first: the finer level is entry e - 1, the
+    // coarser one (if any) e + 1.  Its fields are read before knowing whether it exists (the
+    // table has zeroed entries after its end), so that every table read is issued at once.
+    ConstLevelDev& D = level_entry(a.lv, e);
+    ConstLevelDev& S = level_entry(a.lv, e - 1);
+    ConstLevelDev& U = level_entry(a.lv, e + 1);
+    const int urows = U.rows, ucols = U.cols, upitch = U.pitch;
+    T* const uYm = (T*)U.Ym;
+    T* const uRm = (T*)U.Rm;
     const int ntx = (D.cols + kTile2 - 1) / kTile2;
     const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
     const bool two = D.parent >= 0;
     int r0 = ti0, r1 = min(ti0 + kTile2, D.rows), q0 = tj0, q1 = min(tj0 + kTile2, D.cols);
     int a2 = 0, b2 = 0, c2 = 0, d2 = 0;
     if (two) {
-        ConstLevelDev& U = level_entry(a.lv, D.parent);
         a2 = ti0 / 2;
-        b2 = min(a2 + kTile2 / 2, U.rows);
+        b2 = min(a2 + kTile2 / 2, urows);
         c2 = tj0 / 2;
-        d2 = min(c2 + kTile2 / 2, U.cols);
+        d2 = min(c2 + kTile2 / 2, ucols);
         r0 = min(r0, max(2 * a2 - 2, 0));
         r1 = max(r1, min(2 * b2 + 1, D.rows));
         q0 = min(q0, max(2 * c2 - 2, 0));
@@ -851,7 +858,6 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     }
     if (!two) return;
     __syncthreads();
-    ConstLevelDev& U = level_entry(a.lv, D.parent);
     const int i = a2 + p / (kTile2 / 2), j = c2 + p % (kTile2 / 2);
     if (p >= (kTile2 / 2) * (kTile2 / 2) || i >= b2 || j >= d2) return;
     auto from_lds = [&](int ii, int jj, float& y, float& r) {
@@ -860,8 +866,8 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     };
     float y, r;
     pyr_sample(from_lds, i, j, D.rows, D.cols, y, r);
-    stv((T*)U.Ym, (size_t)i * U.pitch + j, y);
-    stv((T*)U.Rm, (size_t)i * U.pitch + j, r);
+    stv(uYm, (size_t)i * upitch + j, y);
+    stv(uRm, (size_t)i * upitch + j, r);
 }
 
 // first frame: Yhat = G * Y, rho = measured (0 where missing), w = dw = 0, into state[0]
@@ -931,14 +937,27 @@ __device__ __forceinline__ void emit_flow(const ElemArgs& a, int k, ConstLevelDe
 
 // reconstruction w_h = bilinear(w_{h+1}) at (i/2, j/2) + dw_h, in state[parity]
 // Bilinear sample of the coarser level at fine pixel (i, j); `W(ii, jj)` reads it as stored.
-template <class Load>
-__device__ __forceinline__ float bilerp_up(Load W, int i, int j, int urows, int ucols) {
-    const int i0 = i >> 1, j0 = j >> 1;
-    const int i1 = min(i0 + 1, urows - 1), j1 = min(j0 + 1, ucols - 1);
+// The four coarse samples (i0|i1, j0|j1) and their weights.
+struct Bilerp {
+    int i0, i1, j0, j1;
+    float w00, w01, w10, w11;
+};
+__device__ __forceinline__ Bilerp bilerp_at(int i, int j, int urows, int ucols) {
+    Bilerp b;
+    b.i0 = i >> 1;
+    b.j0 = j >> 1;
+    b.i1 = min(b.i0 + 1, urows - 1);
+    b.j1 = min(b.j0 + 1, ucols - 1);
     const float fi = (i & 1) ? 0.5f : 0.0f, fj = (j & 1) ? 0.5f : 0.0f;
-    const float w00 = (1.0f - fi) * (1.0f - fj), w01 = (1.0f - fi) * fj;
-    const float w10 = fi * (1.0f - fj), w11 = fi * fj;
-    return w00 * W(i0, j0) + w01 * W(i0, j1) + w10 * W(i1, j0) + w11 * W(i1, j1);
+    b.w00 = (1.0f - fi) * (1.0f - fj);
+    b.w01 = (1.0f - fi) * fj;
+    b.w10 = fi * (1.0f - fj);
+    b.w11 = fi * fj;
+    return b;
+}
+__device__ __forceinline__ float bilerp_sum(const Bilerp& b, float v00, float v01, float v10,
+                                            float v11) {
+    return b.w00 * v00 + b.w01 * v01 + b.w10 * v10 + b.w11 * v11;
 }
 
 // Two reconstruction levels per launch: the entry is level h, U its parent.  A block owns a
@@ -954,9 +973,17 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     __shared__ float pw[3][P][P + 1];
     int slot, t;
     const int e = tile_entry(a, slot, t);
+    // a stream's entries are consecutive, finest first: U = e + 1 always exists here, its
+    // parent V = e + 2 only below the top (else the next stream's first level or a zeroed pad
+    // entry, read but not used), so that every table read is issued at once
     ConstLevelDev& L = level_entry(a.lv, e);
-    ConstLevelDev& U = level_entry(a.lv, L.parent);
+    ConstLevelDev& U = level_entry(a.lv, e + 1);
+    ConstLevelDev& V = level_entry(a.lv, e + 2);
     const int q = a.parity;
+    const bool utop = U.top != 0;
+    const int vrows = V.rows, vcols = V.cols, vpitch = V.pitch;
+    const T* const vw[3] = {(const T*)V.w[q][0], (const T*)V.w[q][1], (const T*)V.w[q][2]};
+    const float vin = flow_in_scale<T>(V);
     const int ntx = (L.cols + kTile2 - 1) / kTile2;
     const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
     const int ti1 = min(ti0 + kTile2, L.rows), tj1 = min(tj0 + kTile2, L.cols);
@@ -974,18 +1001,27 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     if ((int)threadIdx.x < np) {
         const int ui = pa + threadIdx.x / (pd - pc), uj = pc + threadIdx.x % (pd - pc);
         const size_t uo = (size_t)ui * U.pitch + uj;
-        if (U.top) {
+        if (utop) {
             for (int k = 0; k < 3; ++k) pw[k][ui - pa][uj - pc] = ldv((const T*)U.w[q][k], uo);
         } else {
-            ConstLevelDev& V = level_entry(a.lv, U.parent);
-            const float vin = flow_in_scale<T>(V), uin = flow_in_scale<T>(U);
+            // every load first (the stores below may alias them for all the compiler knows)
+            const Bilerp bv = bilerp_at(ui, uj, vrows, vcols);
+            float s00[3], s01[3], s10[3], s11[3], du[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s00[k] = ldv(vw[k], (size_t)bv.i0 * vpitch + bv.j0);
+                s01[k] = ldv(vw[k], (size_t)bv.i0 * vpitch + bv.j1);
+                s10[k] = ldv(vw[k], (size_t)bv.i1 * vpitch + bv.j0);
+                s11[k] = ldv(vw[k], (size_t)bv.i1 * vpitch + bv.j1);
+                du[k] = ldv((const T*)U.dw[q][k], uo);
+            }
+            const float uin = flow_in_scale<T>(U);
             const float uout = flow_out_scale<T>(U);
             const bool wr = 2 * ui >= ti0 && 2 * ui < ti1 && 2 * uj >= tj0 && 2 * uj < tj1;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const T* W = (const T*)V.w[q][k];
-                auto ld = [&](int ii, int jj) { return ldv(W, (size_t)ii * V.pitch + jj); };
-                const float c = bilerp_up(ld, ui, uj, V.rows, V.cols);
-                const float v = (c * vin + ldv((const T*)U.dw[q][k], uo) * uin) * uout;
+                const float c = bilerp_sum(bv, s00[k], s01[k], s10[k], s11[k]);
+                const float v = (c * vin + du[k] * uin) * uout;
                 pw[k][ui - pa][uj - pc] = rnd<T>(v);
                 if (wr) stv((T*)U.w[q][k], uo, v);
             }
@@ -996,10 +1032,11 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     const float uin = flow_in_scale<T>(U);
     const float lin = flow_in_scale<T>(L);
     const float lout = flow_out_scale<T>(L);
+    const Bilerp bu = bilerp_at(i, j, U.rows, U.cols);
     float w[3];
     for (int k = 0; k < 3; ++k) {
-        auto ld = [&](int ii, int jj) { return pw[k][ii - pa][jj - pc]; };
-        const float c = bilerp_up(ld, i, j, U.rows, U.cols);
+        const float c = bilerp_sum(bu, pw[k][bu.i0 - pa][bu.j0 - pc], pw[k][bu.i0 - pa][bu.j1 - pc],
+                                   pw[k][bu.i1 - pa][bu.j0 - pc], pw[k][bu.i1 - pa][bu.j1 - pc]);
         const float v = c * uin + d[k] * lin;
         stv((T*)L.w[q][k], go, v * lout);
         w[k] = rnd<T>(v * lout) * lin;    // as k_output reads it back
