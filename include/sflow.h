@@ -239,8 +239,8 @@ sf_status sf_set_learned(sf_ctx ctx, const float* params, size_t n, float thresh
 sf_status sf_learned_stats(sf_ctx ctx, int64_t* fallbacks, int64_t* pixels, int32_t reset);
 /* Training data of the last frame of one stream (finest level): writes
  * SF_UPDATE_INPUT_PLANES float32 planes of rows x cols to the device pointer out: the network
- * inputs (9), x0 (3), x_ls (3), S(x_ls) (3), the parent's reconstructed flow (3; 0 at a top
- * level) and dmu (1).  Flows are in rad/frame, so the network output that reaches a flow w is
+ * inputs (9, as the network reads them: rounded to BF16), x0 (3), x_ls (3), S(x_ls) (3), the
+ * parent's reconstructed flow (3; 0 at a top level) and dmu (1).  Flows are in rad/frame, so the network output that reaches a flow w is
  * (w - parent - S(x_ls)) / dmu.  SF_ERR_STATE before the second frame. */
 sf_status sf_get_update_inputs(sf_ctx ctx, int32_t stream, float* out);
 

@@ -76,6 +76,7 @@ struct sf_ctx_s {
     float threshold = 1.0f;
     CnnSegs segs{};
     float* lbuf = nullptr;               // kLearnPlanes x ltotal
+    uint16_t* lpack = nullptr;           // the network's input, BF16 NHWC 16 (in lbuf's allocation)
     uint16_t* act[2] = {nullptr, nullptr};   // BF16 NHWC 16-channel activations
     uint16_t* wf = nullptr;              // packed forward weights [4][9][16][16]
     uint16_t* wb = nullptr;
@@ -412,7 +413,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         sg.total = b;
         size_t lb_bytes = (size_t)kLearnPlanes * b * sizeof(float);
         size_t act_bytes = (size_t)b * 16 * sizeof(uint16_t);
-        size_t need = lb_bytes + 2 * act_bytes + 2 * 4 * 9 * 256 * sizeof(uint16_t) +
+        size_t need = lb_bytes + 3 * act_bytes + 2 * 4 * 9 * 256 * sizeof(uint16_t) +
                       4 * 16 * sizeof(float) + kCnnParams * sizeof(float) + 64 + 6 * 256;
         hipError_t e2 = hipMalloc((void**)&ctx->lbuf, need);
         if (e2 != hipSuccess) {
@@ -426,6 +427,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         char* q = (char*)ctx->lbuf + al(lb_bytes);
         ctx->act[0] = (uint16_t*)q; q += al(act_bytes);
         ctx->act[1] = (uint16_t*)q; q += al(act_bytes);
+        ctx->lpack = (uint16_t*)q; q += al(act_bytes);
         ctx->wf = (uint16_t*)q; q += al(4 * 9 * 256 * sizeof(uint16_t));
         ctx->wb = (uint16_t*)q; q += al(4 * 9 * 256 * sizeof(uint16_t));
         ctx->cnn_bias = (float*)q; q += al(4 * 16 * sizeof(float));
@@ -437,6 +439,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
             L.lbase = sg.base[s];
             L.ltotal = b;
             L.lbuf = ctx->lbuf;
+            L.lpack = ctx->lpack;
         }
         e2 = hipMemsetAsync(ctx->lbuf, 0, need, ctx->stream);
         if (e2 != hipSuccess) {
@@ -716,11 +719,10 @@ static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias
 // network on the finest level of every stream, then the per-pixel choice, smoothing and store
 static sf_status run_learned(sf_ctx c, int q) {
     const int P = c->segs.total;
-    HIP_TRY(c, launch_pack_inputs(c->lbuf + (size_t)kLearnIn * P, kCnnInputs, P, c->act[0], c->stream));
     for (int l = 0; l < kCnnLayers; ++l) {
         ConvArgs a{};
         a.segs = c->segs;
-        a.in = c->act[l & 1];
+        a.in = l == 0 ? c->lpack : c->act[l & 1];   // layer 0: the input the level step packed
         a.w = c->wf + (size_t)l * 9 * 256;
         a.bias = c->cnn_bias + l * 16;
         a.relu = l < kCnnLayers - 1;

@@ -22,11 +22,20 @@ constexpr size_t kLdsBytes = kLdsXB > kLdsPlanes ? kLdsXB : kLdsPlanes;
 constexpr int kMaxStreams = 64;        // camera streams per context
 constexpr int kLevelPad = 2;           // zeroed entries after the device level table
 constexpr int kDefaultPassSteps = 8;   // prediction steps per step launch before a level splits
-// Planes of the learned-update buffers of a finest level: network inputs (6), prior x0 (3),
-// least-squares solution (3), cost terms a_Y (3), a_rho (3), G1, G2 (2) and the network's
-// output (3), each `ltotal` floats.
+// FP32 -> BF16, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Planes of the learned-update buffers of a finest level, each `ltotal` floats: 9 unused (the
+// network's 9 inputs go to `lpack`, BF16), prior x0 (3), least-squares solution (3), cost terms
+// a_Y (3), a_rho (3), G1, G2 (2), the network's output (3), the smoothed solution (3) and the
+// applied correction (3).
 constexpr int kLearnInputs = 9;
-constexpr int kLearnIn = 0, kLearnX0 = 9, kLearnXP = 12, kLearnFB = 15, kLearnOut = 23;
+constexpr int kLearnX0 = 9, kLearnXP = 12, kLearnFB = 15, kLearnOut = 23;
 constexpr int kLearnXS = 26;      // smoothed least-squares solution (the state)
 constexpr int kLearnCorr = 29;    // applied correction, rad/frame (0 where it fell back)
 constexpr int kLearnPlanes = 32;
@@ -54,6 +63,7 @@ struct LevelDev {
     int lbase;                       // first pixel of this level in the learned buffers
     int ltotal;                      // pixels (padded) of the learned buffers, all streams
     float* lbuf;                     // learned buffers: kLearnPlanes planes of ltotal floats
+    uint16_t* lpack;                 // the network's input: BF16, 16 channels per pixel (9 used)
     void* w[2][3];                   // state, indexed by parity
     void* dw[2][3];                  // lower levels only
     void* rho[2];

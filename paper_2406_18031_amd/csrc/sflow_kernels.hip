@@ -647,15 +647,17 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
                     // the cost terms that judge the network's answer
                     float* lb = L.lbuf + L.lbase + (size_t)(i * C + j);
                     const size_t P = (size_t)L.ltotal;
-                    lb[(kLearnIn + 0) * P] = Yprior - 0.5f;
-                    lb[(kLearnIn + 1) * P] = Yh - 0.5f;
-                    lb[(kLearnIn + 2) * P] = rv ? 4.0f * rc : 0.0f;
-                    lb[(kLearnIn + 3) * P] = x0 * 0.25f;
-                    lb[(kLearnIn + 4) * P] = y0 * 0.25f;
-                    lb[(kLearnIn + 5) * P] = z0 * 0.25f;
-                    lb[(kLearnIn + 6) * P] = F[r][KX] * idmu * 0.25f;
-                    lb[(kLearnIn + 7) * P] = F[r][KX + 1] * idmu * 0.25f;
-                    lb[(kLearnIn + 8) * P] = F[r][KX + 2] * idmu * 0.25f;
+                    // the network's input, packed as its first layer reads it
+                    const uint32_t h0 = to_bf16(Yprior - 0.5f), h1 = to_bf16(Yh - 0.5f);
+                    const uint32_t h2 = to_bf16(rv ? 4.0f * rc : 0.0f), h3 = to_bf16(x0 * 0.25f);
+                    const uint32_t h4 = to_bf16(y0 * 0.25f), h5 = to_bf16(z0 * 0.25f);
+                    const uint32_t h6 = to_bf16(F[r][KX] * idmu * 0.25f);
+                    const uint32_t h7 = to_bf16(F[r][KX + 1] * idmu * 0.25f);
+                    const uint32_t h8 = to_bf16(F[r][KX + 2] * idmu * 0.25f);
+                    uint4* pk = reinterpret_cast<uint4*>(L.lpack + ((size_t)L.lbase + i * C + j) * 16);
+                    pk[0] = make_uint4(h0 | (h1 << 16), h2 | (h3 << 16), h4 | (h5 << 16),
+                                       h6 | (h7 << 16));
+                    pk[1] = make_uint4(h8, 0u, 0u, 0u);
                     lb[(kLearnX0 + 0) * P] = px0;
                     lb[(kLearnX0 + 1) * P] = py0;
                     lb[(kLearnX0 + 2) * P] = pz0;
@@ -1104,6 +1106,21 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
         const int li = (i - gi0) * RW + (j - gj0);
         for (int c = 0; c < 3; ++c) X[c][li] = lb[(kLearnXP + c) * P + p];
     }
+    // the network's output and the cost terms of this thread's tile pixels, loaded now so that
+    // their latency hides behind the smoothing (tile pixel q = threadIdx.x + 256 m)
+    constexpr int kPer = kCombTile * kCombTile / 256;
+    const int tw = tj1 - tj0, npx = (ti1 - ti0) * tw;
+    float pre[kPer][11];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+        const int q = threadIdx.x + 256 * m;
+        const int qq = q < npx ? q : 0;
+        const size_t p = (size_t)(ti0 + qq / tw) * C + tj0 + qq % tw;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pre[m][c] = lb[(kLearnOut + c) * P + p];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) pre[m][3 + c] = lb[(kLearnFB + c) * P + p];
+    }
     __syncthreads();
     for (int sp = 1; sp <= Ns; ++sp) {
         const int rad = 2 * (Ns - sp);
@@ -1139,20 +1156,20 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
     const float os = flow_out_scale<T>(L);
     const int q2 = a.parity;
     unsigned int myfb = 0;
-    for (int q = threadIdx.x; q < (ti1 - ti0) * (tj1 - tj0); q += 256) {
-        const int i = ti0 + q / (tj1 - tj0);
-        const int j = tj0 + q % (tj1 - tj0);
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+        const int q = threadIdx.x + 256 * m;
+        if (q >= npx) continue;
+        const int i = ti0 + q / tw;
+        const int j = tj0 + q % tw;
         const size_t p = (size_t)i * C + j;
         const size_t go = (size_t)i * L.pitch + j;
         const int li = (i - gi0) * RW + (j - gj0);
-        float d[3];
-        for (int c = 0; c < 3; ++c) d[c] = lb[(kLearnOut + c) * P + p];   // pixels per frame
-        const float eY = lb[(kLearnFB + 0) * P + p] * d[0] + lb[(kLearnFB + 1) * P + p] * d[1] +
-                         lb[(kLearnFB + 2) * P + p] * d[2];
-        const float eR = lb[(kLearnFB + 3) * P + p] * d[0] + lb[(kLearnFB + 4) * P + p] * d[1] +
-                         lb[(kLearnFB + 5) * P + p] * d[2];
-        const float cost = lb[(kLearnFB + 6) * P + p] * eY * eY +
-                           lb[(kLearnFB + 7) * P + p] * eR * eR +
+        const float* d = pre[m];                      // pixels per frame
+        const float* fbt = pre[m] + 3;
+        const float eY = fbt[0] * d[0] + fbt[1] * d[1] + fbt[2] * d[2];
+        const float eR = fbt[3] * d[0] + fbt[4] * d[1] + fbt[5] * d[2];
+        const float cost = fbt[6] * eY * eY + fbt[7] * eR * eR +
                            L.g3 * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         const bool fb = !(cost <= a.threshold) || !isfinite(cost);   // NaN and inf fall back
         myfb += fb ? 1u : 0u;
@@ -1183,7 +1200,10 @@ __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     const size_t o = (size_t)i * L.cols + j;
     const size_t P = (size_t)L.ltotal;
     const float* lb = L.lbuf + L.lbase + o;
-    for (int k = 0; k < kLearnFB; ++k) a.out[k * npx + o] = lb[k * P];
+    const uint16_t* pk = L.lpack + ((size_t)L.lbase + o) * 16;
+    for (int k = 0; k < kLearnInputs; ++k)   // the network's inputs, as it reads them (BF16)
+        a.out[k * npx + o] = __builtin_bit_cast(float, (uint32_t)pk[k] << 16);
+    for (int k = kLearnInputs; k < kLearnFB; ++k) a.out[k * npx + o] = lb[k * P];
     for (int k = 0; k < 3; ++k) a.out[(kLearnFB + k) * npx + o] = lb[(kLearnXS + k) * P];
     float base[3] = {0.0f, 0.0f, 0.0f};
     if (!L.top) {
