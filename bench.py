@@ -294,10 +294,11 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_step_boxes512_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2406_18031_amd", "csrc", "sflow_kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per level-step launch from the committed rocprofv3 counter summary (FETCH_SIZE
-    + WRITE_SIZE, scaled by the same counters on a plain copy of known size), or None when the
-    kernel source changed since the counters were taken."""
+def measured_counters():
+    """Values per level-step launch from the committed rocprofv3 counter summary: HBM bytes
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy of known size) and
+    VALU instructions (SQ_INSTS_VALU), or None when the kernel source changed since the counters
+    were taken."""
     import hashlib
     if not os.path.exists(COUNTERS):
         return None
@@ -311,7 +312,9 @@ def measured_traffic():
         sha = hashlib.sha256(fh.read()).hexdigest()
     if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return {"traffic": float(vals["traffic_bytes_per_launch"]),
+            "valu": float(vals["valu_instructions_per_launch"])
+            if "valu_instructions_per_launch" in vals else None}
 
 
 def copy_probe(mib: int, reps: int = 20):
@@ -361,6 +364,7 @@ def main():
     step_flops = sum(L["rows"] * L["cols"] * step_flops_per_px(L["top"], L["N"], L["Ns"])
                      for L in levels)
     step_ms = r["kernel_ms"][1] / max(1, r["kernel_n"][1])
+    counters = measured_counters() if args.workload == "boxes512" else None
     achieved_tflops = step_flops / (step_ms * 1e-3) / 1e12
     achieved_gbs = step_bytes / (step_ms * 1e-3) / 1e9
 
@@ -393,7 +397,7 @@ def main():
             "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_PEAK_TFLOPS,
-            "traffic": measured_traffic() if args.workload == "boxes512" else None,
+            "traffic": counters["traffic"] if counters else None,
             "kernel": "k_step (fused level step, all levels in one launch)",
             "kernel_us": step_ms * 1e3,
             "algorithmic_flops": step_flops,
@@ -401,6 +405,12 @@ def main():
             "hbm_achieved_gbs": achieved_gbs,
             "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
             "frac_of_unpacked_fp32": achieved_tflops / FP32_UNPACKED_TFLOPS,
+            # share of every SIMD's issue cycles spent on VALU instructions over the launch
+            # (SQ_INSTS_VALU of the committed counters, 4 cycles per wave64 instruction, against
+            # 256 CUs x 4 SIMDs x 2.4 GHz x the live kernel time): the instructions the FLOP
+            # model does not count (halo recomputation, lane shifts, selects) included
+            "valu_issue_frac": (counters["valu"] * 4 / (256 * 4 * 2.4e9 * step_ms * 1e-3)
+                                if counters and counters["valu"] else None),
         },
         "kernel_us_per_frame": {k: v / max(1, n) * 1e3 * n / args.steps for k, v, n in
                                 zip(("pyramid", "level_step", "reconstruct"), r["kernel_ms"],
