@@ -798,17 +798,22 @@ __device__ __forceinline__ void pyr_sample(Load ld, int i, int j, int rows, int 
 
 // Two pyramid levels per launch: the entry is level d (>= 1).  A block owns a kTile2 x kTile2
 // tile of level d and, if level d + 1 exists, the kTile2/2 x kTile2/2 tile of level d + 1
-// above it.  Phase 1 computes level d on the tile plus the rows and columns that level d + 1
-// reads (at most kTile2 + 3 per side, one pixel per thread) into LDS, as stored (rounded to
-// T), and writes the tile's own pixels; phase 2 computes level d + 1 from LDS.  Every level-d
-// pixel is written by exactly one block.
+// above it.  The level d - 1 pixels the tile reads (at most 2 (kTile2 + 3) + 3 per side) are
+// staged in LDS first, each loaded once with all of a thread's loads in flight together.
+// Phase 1 computes level d on the tile plus the rows and columns that level d + 1 reads (at
+// most kTile2 + 3 per side, one pixel per thread) into LDS, as stored (rounded to T), and writes
+// the tile's own pixels; phase 2 computes level d + 1 from LDS.  Every level-d pixel is written
+// by exactly one block.
 constexpr int kPyrPatch = kTile2 + 3;
+constexpr int kPyrSrc = 2 * kPyrPatch + 3;
 constexpr int kPyrThreads = 512;
 static_assert(kPyrPatch * kPyrPatch <= kPyrThreads, "one patch pixel per thread");
 template <typename T>
 __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
-    constexpr int P = kPyrPatch;
+    constexpr int P = kPyrPatch, Q = kPyrSrc;
+    constexpr int NL = (Q * Q + kPyrThreads - 1) / kPyrThreads;
     __shared__ float pY[P][P + 1], pR[P][P + 1];
+    __shared__ float sY[Q][Q + 1], sR[Q][Q + 1];
     int k, t;
     const int e = tile_entry(a, k, t);
     // a stream's entries are consecutive, finest first: the finer level is entry e - 1, the
@@ -841,16 +846,38 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     const T* Rs = (const T*)(fin ? a.in.R[D.stream] : S.Rm);
     const int sp = fin ? S.cols : S.pitch;
     const int p = threadIdx.x;
+    // the finer level's rows [s0, s0 + ns) and columns [u0, u0 + nu): every clamped tap
+    const int s0 = max(2 * r0 - 2, 0), ns = min(2 * r1 + 1, S.rows) - s0;
+    const int u0 = max(2 * q0 - 2, 0), nu = min(2 * q1 + 1, S.cols) - u0;
+    {
+        float vy[NL], vr[NL];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int q = p + m * kPyrThreads;
+            const int qq = q < ns * nu ? q : 0;
+            const size_t idx = (size_t)(s0 + qq / nu) * sp + u0 + qq % nu;
+            vy[m] = ldv(Ys, idx);
+            vr[m] = ldv(Rs, idx);
+        }
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int q = p + m * kPyrThreads;
+            if (q < ns * nu) {
+                sY[q / nu][q % nu] = vy[m];
+                sR[q / nu][q % nu] = vr[m];
+            }
+        }
+    }
+    __syncthreads();
     if (p < nr * nc) {
         const int li = p / nc, lj = p - li * nc;
         const int i = r0 + li, j = q0 + lj;
-        auto from_mem = [&](int ii, int jj, float& y, float& r) {
-            const size_t idx = (size_t)ii * sp + jj;
-            y = ldv(Ys, idx);
-            r = ldv(Rs, idx);
+        auto from_src = [&](int ii, int jj, float& y, float& r) {
+            y = sY[ii - s0][jj - u0];
+            r = sR[ii - s0][jj - u0];
         };
         float y, r;
-        pyr_sample(from_mem, i, j, S.rows, S.cols, y, r);
+        pyr_sample(from_src, i, j, S.rows, S.cols, y, r);
         pY[li][lj] = rnd<T>(y);
         pR[li][lj] = rnd<T>(r);
         if (i >= ti0 && i < ti0 + kTile2 && j >= tj0 && j < tj0 + kTile2) {
