@@ -93,6 +93,11 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
         bv[tp] = unpack4(*(const uint2*)(a.w + ((size_t)tp * 16 + col) * 16 + 4 * quad));
     const float bias = a.bias ? a.bias[col] : 0.0f;
     __syncthreads();
+    // results go to an LDS copy of the output tile first, then every thread writes one pixel
+    // whole (two 16-byte stores, or three channel planes), instead of 2-byte stores per lane
+    __shared__ uint4 tile16[kConvTile * kConvTile * 2];   // BF16 [pixel][16 channels]
+    __shared__ float tile32[3][kConvTile * kConvTile];    // FP32 [channel][pixel]
+    uint16_t* t16 = reinterpret_cast<uint16_t*>(tile16);
 #pragma unroll
     for (int rr = 0; rr < kConvTile / 4; ++rr) {
         const int row = wave * (kConvTile / 4) + rr;     // tile row of this wave
@@ -104,21 +109,29 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[tp], acc, 0, 0, 0);
         }
         // D[4 (lane / 16) + r][lane % 16]: pixel column 4 quad + r of this row, channel col
-        const int y = ty0 + row;
-        if (y >= rows) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int x = tx0 + 4 * quad + r;
-            if (x >= cols) continue;
-            const size_t i = (size_t)y * cols + x;
+            const int px = row * kConvTile + 4 * quad + r;
             float v = acc[r] + bias;
             if (a.relu) v = fmaxf(v, 0.0f);
             if (OUT_F32) {
-                if (col < a.nout) a.out_f32[(size_t)col * a.segs.total + base + i] = v;
+                if (col < 3) tile32[col][px] = v;
             } else {
-                a.out[((size_t)base + i) * 16 + col] = col < a.nout ? f2bf(v) : (uint16_t)0;
+                t16[px * 16 + col] = col < a.nout ? f2bf(v) : (uint16_t)0;
             }
         }
+    }
+    __syncthreads();
+    const int px = threadIdx.x;                           // one pixel of the tile per thread
+    const int y = ty0 + px / kConvTile, x = tx0 + px % kConvTile;
+    if (y >= rows || x >= cols) return;
+    const size_t i = (size_t)base + (size_t)y * cols + x;
+    if (OUT_F32) {
+        for (int c = 0; c < a.nout && c < 3; ++c) a.out_f32[(size_t)c * a.segs.total + i] = tile32[c][px];
+    } else {
+        uint4* o = reinterpret_cast<uint4*>(a.out + i * 16);
+        o[0] = tile16[px * 2];
+        o[1] = tile16[px * 2 + 1];
     }
 }
 
