@@ -65,22 +65,35 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     const int t = b - a.tblk[sgi];
     const int tiles_x = (cols + kConvTile - 1) / kConvTile;
     const int ty0 = (t / tiles_x) * kConvTile, tx0 = (t % tiles_x) * kConvTile;
-    for (int q = threadIdx.x; q < kConvPatch * kConvPatch * 4; q += 256) {
-        const int px = q >> 2, quad = q & 3;
-        const int yy = ty0 - 1 + px / kConvPatch, xx = tx0 - 1 + px % kConvPatch;
-        uint2 v = make_uint2(0u, 0u);
-        if (yy >= 0 && yy < rows && xx >= 0 && xx < cols) {
-            const size_t off = ((size_t)base + (size_t)yy * cols + xx) * 16 + quad * 4;
-            v = *(const uint2*)(a.in + off);
-            if (a.mask) {
-                const uint2 m = *(const uint2*)(a.mask + off);
-                if (bf2f((uint16_t)(m.x & 0xffff)) <= 0.0f) v.x &= 0xffff0000u;
-                if (bf2f((uint16_t)(m.x >> 16)) <= 0.0f) v.x &= 0x0000ffffu;
-                if (bf2f((uint16_t)(m.y & 0xffff)) <= 0.0f) v.y &= 0xffff0000u;
-                if (bf2f((uint16_t)(m.y >> 16)) <= 0.0f) v.y &= 0x0000ffffu;
-            }
+    {   // every load of the patch in flight together (addresses outside the image read the
+        // first pixel and are zeroed), then the LDS stores
+        constexpr int NQ = kConvPatch * kConvPatch * 4, NL = (NQ + 255) / 256;
+        uint2 vv[NL], mm[NL];
+        bool inb[NL];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int q = threadIdx.x + 256 * m;
+            const int px = q >> 2, quad = q & 3;
+            const int yy = ty0 - 1 + px / kConvPatch, xx = tx0 - 1 + px % kConvPatch;
+            inb[m] = q < NQ && yy >= 0 && yy < rows && xx >= 0 && xx < cols;
+            const size_t off = inb[m] ? ((size_t)base + (size_t)yy * cols + xx) * 16 + quad * 4 : 0;
+            vv[m] = *(const uint2*)(a.in + off);
+            if (a.mask) mm[m] = *(const uint2*)(a.mask + off);
         }
-        patch[q] = v;
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int q = threadIdx.x + 256 * m;
+            if (q >= NQ) continue;
+            uint2 v = inb[m] ? vv[m] : make_uint2(0u, 0u);
+            if (a.mask) {
+                const uint2 mk = mm[m];
+                if (bf2f((uint16_t)(mk.x & 0xffff)) <= 0.0f) v.x &= 0xffff0000u;
+                if (bf2f((uint16_t)(mk.x >> 16)) <= 0.0f) v.x &= 0x0000ffffu;
+                if (bf2f((uint16_t)(mk.y & 0xffff)) <= 0.0f) v.y &= 0xffff0000u;
+                if (bf2f((uint16_t)(mk.y >> 16)) <= 0.0f) v.y &= 0x0000ffffu;
+            }
+            patch[q] = v;
+        }
     }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
