@@ -117,7 +117,9 @@ hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds_bytes,
                        hipStream_t s);
-hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s);
+// tile: kTile2 (one level-h pixel per thread) or 2 kTile2 (four); the blocks in a.blk count
+// tiles of that size
+hipError_t launch_reconstruct(int storage, int tile, const ElemArgs& a, hipStream_t s);
 hipError_t launch_output(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_learned_extract(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t prepare_kernels(size_t max_lds_bytes);

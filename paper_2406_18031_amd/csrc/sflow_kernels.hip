@@ -996,9 +996,11 @@ __device__ __forceinline__ float bilerp_sum(const Bilerp& b, float v00, float v0
 // every U pixel is written once), read from the state otherwise.  Phase 2 reconstructs level h
 // and, for the launch slots whose a.outs is set, writes their stream's output (emit_flow),
 // bitwise what k_output would write after this launch.
-template <typename T>
+template <typename T, int TILE>
 __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
-    constexpr int P = kTile2 / 2 + 1;
+    constexpr int P = TILE / 2 + 1;
+    constexpr int NPX = TILE * TILE / kElemBlock;                  // level-h pixels per thread
+    constexpr int NPP = (P * P + kElemBlock - 1) / kElemBlock;     // footprint pixels per thread
     __shared__ float pw[3][P][P + 1];
     int slot, t;
     const int e = tile_entry(a, slot, t);
@@ -1013,64 +1015,97 @@ __global__ void __launch_bounds__(kElemBlock) k_reconstruct(ElemArgs a) {
     const int vrows = V.rows, vcols = V.cols, vpitch = V.pitch;
     const T* const vw[3] = {(const T*)V.w[q][0], (const T*)V.w[q][1], (const T*)V.w[q][2]};
     const float vin = flow_in_scale<T>(V);
-    const int ntx = (L.cols + kTile2 - 1) / kTile2;
-    const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
-    const int ti1 = min(ti0 + kTile2, L.rows), tj1 = min(tj0 + kTile2, L.cols);
+    const int ntx = (L.cols + TILE - 1) / TILE;
+    const int ti0 = (t / ntx) * TILE, tj0 = (t % ntx) * TILE;
+    const int ti1 = min(ti0 + TILE, L.rows), tj1 = min(tj0 + TILE, L.cols);
     const int pa = ti0 >> 1, pb = min(((ti1 - 1) >> 1) + 2, U.rows);
     const int pc = tj0 >> 1, pd = min(((tj1 - 1) >> 1) + 2, U.cols);
     const int np = (pb - pa) * (pd - pc);
-    // level-h pixel of this thread, its increment loaded before the barrier
-    const int li = threadIdx.x / kTile2, lj = threadIdx.x % kTile2;
-    const int i = ti0 + li, j = tj0 + lj;
-    const bool own = i < ti1 && j < tj1;
-    const size_t go = (size_t)i * L.pitch + j;
-    float d[3] = {0.0f, 0.0f, 0.0f};
-    if (own)
-        for (int k = 0; k < 3; ++k) d[k] = ldv((const T*)L.dw[q][k], go);
-    if ((int)threadIdx.x < np) {
-        const int ui = pa + threadIdx.x / (pd - pc), uj = pc + threadIdx.x % (pd - pc);
-        const size_t uo = (size_t)ui * U.pitch + uj;
-        if (utop) {
+    // the level-h pixels of this thread (threadIdx.x + 256 m), their increments loaded before
+    // the barrier
+    float d[NPX][3];
+#pragma unroll
+    for (int m = 0; m < NPX; ++m) {
+        const int px = threadIdx.x + kElemBlock * m;
+        const int i = ti0 + px / TILE, j = tj0 + px % TILE;
+        const size_t go = (size_t)i * L.pitch + j;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d[m][k] = 0.0f;
+        if (i < ti1 && j < tj1)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) d[m][k] = ldv((const T*)L.dw[q][k], go);
+    }
+    if (utop) {
+#pragma unroll
+        for (int m = 0; m < NPP; ++m) {
+            const int pp = threadIdx.x + kElemBlock * m;
+            if (pp >= np) continue;
+            const int ui = pa + pp / (pd - pc), uj = pc + pp % (pd - pc);
+            const size_t uo = (size_t)ui * U.pitch + uj;
             for (int k = 0; k < 3; ++k) pw[k][ui - pa][uj - pc] = ldv((const T*)U.w[q][k], uo);
-        } else {
-            // every load first (the stores below may alias them for all the compiler knows)
-            const Bilerp bv = bilerp_at(ui, uj, vrows, vcols);
-            float s00[3], s01[3], s10[3], s11[3], du[3];
+        }
+    } else {
+        // every load first (the stores below may alias them for all the compiler knows);
+        // footprint pixels past np load pixel (pa, pc) and are dropped
+        Bilerp bv[NPP];
+        float s00[NPP][3], s01[NPP][3], s10[NPP][3], s11[NPP][3], du[NPP][3];
+#pragma unroll
+        for (int m = 0; m < NPP; ++m) {
+            const int pp = threadIdx.x + kElemBlock * m;
+            const int ppc = pp < np ? pp : 0;
+            const int ui = pa + ppc / (pd - pc), uj = pc + ppc % (pd - pc);
+            const size_t uo = (size_t)ui * U.pitch + uj;
+            bv[m] = bilerp_at(ui, uj, vrows, vcols);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                s00[k] = ldv(vw[k], (size_t)bv.i0 * vpitch + bv.j0);
-                s01[k] = ldv(vw[k], (size_t)bv.i0 * vpitch + bv.j1);
-                s10[k] = ldv(vw[k], (size_t)bv.i1 * vpitch + bv.j0);
-                s11[k] = ldv(vw[k], (size_t)bv.i1 * vpitch + bv.j1);
-                du[k] = ldv((const T*)U.dw[q][k], uo);
+                s00[m][k] = ldv(vw[k], (size_t)bv[m].i0 * vpitch + bv[m].j0);
+                s01[m][k] = ldv(vw[k], (size_t)bv[m].i0 * vpitch + bv[m].j1);
+                s10[m][k] = ldv(vw[k], (size_t)bv[m].i1 * vpitch + bv[m].j0);
+                s11[m][k] = ldv(vw[k], (size_t)bv[m].i1 * vpitch + bv[m].j1);
+                du[m][k] = ldv((const T*)U.dw[q][k], uo);
             }
-            const float uin = flow_in_scale<T>(U);
-            const float uout = flow_out_scale<T>(U);
+        }
+        const float uin = flow_in_scale<T>(U);
+        const float uout = flow_out_scale<T>(U);
+#pragma unroll
+        for (int m = 0; m < NPP; ++m) {
+            const int pp = threadIdx.x + kElemBlock * m;
+            if (pp >= np) continue;
+            const int ui = pa + pp / (pd - pc), uj = pc + pp % (pd - pc);
+            const size_t uo = (size_t)ui * U.pitch + uj;
             const bool wr = 2 * ui >= ti0 && 2 * ui < ti1 && 2 * uj >= tj0 && 2 * uj < tj1;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const float c = bilerp_sum(bv, s00[k], s01[k], s10[k], s11[k]);
-                const float v = (c * vin + du[k] * uin) * uout;
+                const float c = bilerp_sum(bv[m], s00[m][k], s01[m][k], s10[m][k], s11[m][k]);
+                const float v = (c * vin + du[m][k] * uin) * uout;
                 pw[k][ui - pa][uj - pc] = rnd<T>(v);
                 if (wr) stv((T*)U.w[q][k], uo, v);
             }
         }
     }
     __syncthreads();
-    if (!own) return;
     const float uin = flow_in_scale<T>(U);
     const float lin = flow_in_scale<T>(L);
     const float lout = flow_out_scale<T>(L);
-    const Bilerp bu = bilerp_at(i, j, U.rows, U.cols);
-    float w[3];
-    for (int k = 0; k < 3; ++k) {
-        const float c = bilerp_sum(bu, pw[k][bu.i0 - pa][bu.j0 - pc], pw[k][bu.i0 - pa][bu.j1 - pc],
-                                   pw[k][bu.i1 - pa][bu.j0 - pc], pw[k][bu.i1 - pa][bu.j1 - pc]);
-        const float v = c * uin + d[k] * lin;
-        stv((T*)L.w[q][k], go, v * lout);
-        w[k] = rnd<T>(v * lout) * lin;    // as k_output reads it back
+#pragma unroll
+    for (int m = 0; m < NPX; ++m) {
+        const int px = threadIdx.x + kElemBlock * m;
+        const int i = ti0 + px / TILE, j = tj0 + px % TILE;
+        if (i >= ti1 || j >= tj1) continue;
+        const size_t go = (size_t)i * L.pitch + j;
+        const Bilerp bu = bilerp_at(i, j, U.rows, U.cols);
+        float w[3];
+        for (int k = 0; k < 3; ++k) {
+            const float c = bilerp_sum(bu, pw[k][bu.i0 - pa][bu.j0 - pc],
+                                       pw[k][bu.i0 - pa][bu.j1 - pc],
+                                       pw[k][bu.i1 - pa][bu.j0 - pc],
+                                       pw[k][bu.i1 - pa][bu.j1 - pc]);
+            const float v = c * uin + d[m][k] * lin;
+            stv((T*)L.w[q][k], go, v * lout);
+            w[k] = rnd<T>(v * lout) * lin;    // as k_output reads it back
+        }
+        if (a.outs[slot]) emit_flow(a, slot, L, i, j, w[0], w[1], w[2]);
     }
-    if (a.outs[slot]) emit_flow(a, slot, L, i, j, w[0], w[1], w[2]);
 }
 
 // finest-level outputs of the streams of the launch (entries with a.outs set)
@@ -1295,12 +1330,20 @@ hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds, 
     return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(int storage, const ElemArgs& a, hipStream_t s) {
+hipError_t launch_reconstruct(int storage, int tile, const ElemArgs& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_reconstruct<__half>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_reconstruct<float>, dim3(elem_blocks(a)), dim3(kElemBlock), 0, s, a);
+    const dim3 g(elem_blocks(a)), b(kElemBlock);
+    if (tile == 2 * kTile2) {
+        if (storage == SF_FP16)
+            hipLaunchKernelGGL((k_reconstruct<__half, 2 * kTile2>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_reconstruct<float, 2 * kTile2>), g, b, 0, s, a);
+    } else {
+        if (storage == SF_FP16)
+            hipLaunchKernelGGL((k_reconstruct<__half, kTile2>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_reconstruct<float, kTile2>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -130,3 +130,52 @@ def test_autotuned_launch_shape_keeps_results():
             a = plain.flow(s, sflow.SF_FLOW_W_FRAME).cpu().numpy()
             b = tuned.flow(s, sflow.SF_FLOW_W_FRAME).cpu().numpy()
             assert np.array_equal(a, b), (k, s)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_large_batch_reconstruction_tile(storage):
+    """A batch whose finest reconstruction covers at least 4096 16 x 16 tiles runs it on 32 x 32
+    tiles (four pixels per thread); a stream alone runs it on 16 x 16 tiles.  Both give bitwise
+    the same flow and state, on ragged sizes, with and without a parent above the upper level."""
+    from paper_2406_18031_amd import sflow
+    dtype = np.float16 if storage == 1 else np.float32
+    kinds = [
+        dict(rows=250, cols=270, levels=3, max_flow_px=8.0, smooth=[2, 4, 4],
+             camera=(200.0, 200.0, 134.5, 124.5)),          # 272 tiles at level 0
+        dict(rows=301, cols=199, levels=2, max_flow_px=4.0, smooth=[2, 3],
+             camera=(180.0, 180.0, 99.0, 150.0)),           # 247, the upper level is the top
+        dict(rows=333, cols=250, levels=4, max_flow_px=16.0, smooth=[2, 4, 4, 4],
+             camera=(220.0, 220.0, 124.5, 166.0)),          # 336
+        dict(rows=100, cols=100, levels=1, max_flow_px=2.0, smooth=[2],
+             camera=(60.0, 60.0, 49.5, 49.5)),              # no reconstruction
+    ]
+    specs = kinds * 5
+    tiles = sum(((sp["rows"] + 15) // 16) * ((sp["cols"] + 15) // 16)
+                for sp in specs if sp["levels"] >= 2)
+    assert tiles >= 4096 and all(((sp["rows"] + 15) // 16) * ((sp["cols"] + 15) // 16) < 4096
+                                 for sp in specs)
+    rng = np.random.default_rng(57)
+    nfr = 3
+    frames = [_frames(rng, sp, nfr) for sp in specs]
+    log(f"storage {storage}: batch of {len(specs)} streams, {tiles} tiles")
+    batch = sflow.Batch(specs, storage=storage)
+    singles = [sflow.Filter(sp["rows"], sp["cols"], sp["levels"], sp["max_flow_px"], sp["smooth"],
+                            *sp["camera"], storage=storage) for sp in specs]
+    for k in range(nfr):
+        dev = [(to_dev(fr[k][0], dtype), to_dev(fr[k][1], dtype)) for fr in frames]
+        dts = [0.01 * (1 + (s + k) % 3) for s in range(len(specs))]
+        batch.push([d[0] for d in dev], [d[1] for d in dev], dts)
+        for s, f in enumerate(singles):
+            f.push(dev[s][0], dev[s][1], dts[s])
+        got = batch.flows(sflow.SF_FLOW_W_FRAME)
+        for s, f in enumerate(singles):
+            a, b = got[s].cpu().numpy(), f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
+            assert np.array_equal(a, b, equal_nan=True), (k, s)
+    for s, f in enumerate(singles):
+        sa, sb = batch.get_state(s)[0], f.get_state()[0]
+        for la, lb in zip(sa, sb):
+            for key in la:
+                assert np.array_equal(la[key], lb[key], equal_nan=True), (s, key)
+    batch.close()
+    for f in singles:
+        f.close()
