@@ -179,3 +179,82 @@ def test_large_batch_reconstruction_tile(storage):
     batch.close()
     for f in singles:
         f.close()
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_stream_mix_workload(storage):
+    """The 64-stream mix (256x256, 512x512 and 1024x1024 box scenes, 3-4 levels) at full size in
+    the launch configuration the bench times (autotuned pass length and tiles, outputs of all
+    streams in one call): every stream bitwise equal to the stream run alone, and the first
+    256x256 and 512x512 streams (in FP32 storage also the first two frames of the first
+    1024x1024 one, about 30 s of oracle time) against the oracle on every pixel."""
+    import torch
+    from oracle import Filter as Oracle
+    from paper_2406_18031_amd import sflow, tune
+    from synth.workloads import stream_mix
+    from gpu_helpers import rounded
+
+    nfr = 3
+    dtype = torch.float16 if storage == 1 else torch.float32
+    mix = stream_mix(64, n_frames=nfr, device="cuda")
+    specs, frames, dt = [], [], None
+    for m in mix:
+        seq = m["build"]()
+        c = seq.camera
+        specs.append(dict(rows=seq.rows, cols=seq.cols, levels=m["levels"],
+                          max_flow_px=m["max_flow_px"], smooth=m["smooth"],
+                          camera=(c.fx, c.fy, c.cx, c.cy)))
+        fr = []
+        for k in range(nfr):
+            f = seq.frame(k, "cuda")
+            fr.append((f.Y.to(dtype).contiguous(), f.rho.to(dtype).contiguous()))
+        frames.append(fr)
+        dt = seq.dt
+    log(f"storage {storage}: {len(specs)} streams, sizes",
+        sorted({sp['rows'] for sp in specs}))
+    batch = sflow.Batch(specs, storage=storage)
+    dts = [dt] * len(specs)
+
+    def push(k):
+        batch.push([fr[k % nfr][0] for fr in frames], [fr[k % nfr][1] for fr in frames], dts)
+
+    big = max(specs, key=lambda sp: sp["rows"] * sp["cols"])
+    lv, r_, c_ = [], big["rows"], big["cols"]
+    for h in range(big["levels"]):
+        lv.append(dict(rows=r_, cols=c_, max_flow_px=big["max_flow_px"], smooth=big["smooth"][h],
+                       h=h))
+        r_, c_ = (r_ + 1) // 2, (c_ + 1) // 2
+    setting = tune.tune(batch.ctx, push, lv)
+    log("tuned:", setting["pass_steps"], setting["tiles"])
+    sflow.sf_set_cameras(batch.ctx, [sp["camera"] for sp in specs])    # restart every stream
+    singles = [sflow.Filter(sp["rows"], sp["cols"], sp["levels"], sp["max_flow_px"], sp["smooth"],
+                            *sp["camera"], storage=storage) for sp in specs]
+    sizes = [sp["rows"] for sp in specs]
+    checked = {sizes.index(256): nfr, sizes.index(512): nfr}
+    if storage == 0:
+        checked[sizes.index(1024)] = 2
+    oracles = {s: Oracle(specs[s]["rows"], specs[s]["cols"], specs[s]["levels"],
+                         specs[s]["max_flow_px"], specs[s]["smooth"], *specs[s]["camera"])
+               for s in checked}
+    bar = 1e-3 if storage == 0 else 2e-2
+    for k in range(nfr):
+        log(f"  frame {k}")
+        push(k)
+        for s, f in enumerate(singles):
+            f.push(frames[s][k][0], frames[s][k][1], dt)
+        got = batch.flows(sflow.SF_FLOW_W_FRAME)
+        for s, f in enumerate(singles):
+            a, b = got[s].cpu().numpy(), f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
+            assert np.array_equal(a, b, equal_nan=True), (k, s)
+        for s, o in oracles.items():
+            if k >= checked[s]:
+                continue
+            Y, rho = (v.to(torch.float32).cpu().numpy() for v in frames[s][k])
+            o.push(rounded(Y, storage), rounded(rho, storage), dt)
+            e = epe_px(got[s].cpu().numpy().transpose(1, 2, 0), o.flow("w_frame"),
+                       o.grids[0].dmu)
+            log(f"    stream {s} ({sizes[s]}^2) mean EPE {e['mean']:.2e} max {e['max']:.2e}")
+            assert e["mean"] <= bar, (k, s, e)
+    batch.close()
+    for f in singles:
+        f.close()
