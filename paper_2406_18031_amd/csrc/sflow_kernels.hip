@@ -135,6 +135,40 @@ __device__ __forceinline__ float dpp_next(float v) {   // value of the lane to t
         __builtin_bit_cast(int, v), 0x130 /* wave_shl:1 */, 0xF, 0xF, true));
 }
 
+// acc[k] -= f[k] of the lane to the right * c, for every k, as v_fmac_f32 with the lane shift
+// on its first source (the compiler folds lane shifts into multiplies and adds but not into
+// fmac).  The compiler does not account for the wait states a shifted read needs after the
+// instruction that wrote its source (2 after a VALU write, 5 after an EXEC write), so the
+// block starts with 5 of its own; the reads inside the block are of registers written before
+// it.  Same rules as dpp_next: every lane active; lanes past the wave's end read 0.
+template <int NF>
+__device__ __forceinline__ void fmac_next_neg(float (&acc)[NF], const float (&f)[NF], float c) {
+    static_assert(NF == 4 || NF == 8, "four or eight fields");
+    if constexpr (NF == 4) {
+        asm("s_nop 4\n\t"
+            "v_fmac_f32_dpp %0, %4, -%8 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %1, %5, -%8 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %2, %6, -%8 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %3, %7, -%8 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+            : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3])
+            : "v"(f[0]), "v"(f[1]), "v"(f[2]), "v"(f[3]), "v"(c));
+    } else {
+        asm("s_nop 4\n\t"
+            "v_fmac_f32_dpp %0, %8, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %1, %9, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %2, %10, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %3, %11, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %4, %12, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %5, %13, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %6, %14, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_fmac_f32_dpp %7, %15, -%16 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+            : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]),
+              "+v"(acc[4]), "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7])
+            : "v"(f[0]), "v"(f[1]), "v"(f[2]), "v"(f[3]),
+              "v"(f[4]), "v"(f[5]), "v"(f[6]), "v"(f[7]), "v"(c));
+    }
+}
+
 // Column neighbours with clamping at the image's left/right border (the border pixel is its
 // own neighbour).  BORDER is false for tiles that touch neither border.
 template <bool BORDER>
@@ -198,8 +232,9 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
         // the upwind side, written as k0 f + ap f_left - am f_right with ap = dt max(u_hat, 0),
         // am = dt min(u_hat, 0), k0 = 1 - dt sigma s - ap + am (no source term for the image).
         // At the image border the missing neighbour equals the pixel itself, so its weight
-        // moves into k0, i.e. the coefficient is dropped.  The two neighbour products are
-        // plain multiplies so that the lane shifts fold into them (4 instructions per field).
+        // moves into k0, i.e. the coefficient is dropped.  Per field: the left neighbour's
+        // product (a multiply with the lane shift folded in), k0 f added by fmac, the right
+        // neighbour's by fmac with the lane shift (3 instructions per field).
         const float du = dt * uh;
         float ap = fmaxf(du, 0.0f), am = fminf(du, 0.0f);
         if (BORDER) {
@@ -212,14 +247,16 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
         const float d = BORDER ? ap - am : fabsf(du);
         const float k0 = c - d;
         const float k1 = 1.0f - d;
+        float acc[NF];
 #pragma unroll
         for (int k = 0; k < NF; ++k) {
             const float f = F[r][k];
-            const float fm = dpp_prev(f);
-            const float fp = dpp_next(f);
             const float kk = (NF == 8 && k == 7) ? k1 : k0;
-            F[r][k] = fmaf(kk, f, fm * ap - fp * am);
+            acc[k] = fmaf(kk, f, dpp_prev(f) * ap);
         }
+        fmac_next_neg<NF>(acc, F[r], am);
+#pragma unroll
+        for (int k = 0; k < NF; ++k) F[r][k] = acc[k];
     }
 }
 
@@ -990,8 +1027,9 @@ __device__ __forceinline__ float bilerp_sum(const Bilerp& b, float v00, float v0
 }
 
 // Two reconstruction levels per launch: the entry is level h, U its parent.  A block owns a
-// kTile2 x kTile2 tile of level h.  Phase 1 holds U on the tile's footprint (at most
-// kTile2/2 + 1 per side) in LDS, as stored: reconstructed from U's parent when U is not the
+// TILE x TILE tile of level h (TILE = 16: one pixel per thread; 32: four, for launches large
+// enough to fill the chip with the bigger tiles).  Phase 1 holds U on the tile's footprint (at
+// most TILE/2 + 1 per side) in LDS, as stored: reconstructed from U's parent when U is not the
 // top level (the block then also writes the U pixels (i, j) with (2i, 2j) in its tile, so
 // every U pixel is written once), read from the state otherwise.  Phase 2 reconstructs level h
 // and, for the launch slots whose a.outs is set, writes their stream's output (emit_flow),
