@@ -311,17 +311,20 @@ static ElemArgs tile_args(sf_ctx c, int level, int above, int parity, int tile =
     return a;
 }
 
-// Tile side of a reconstruction launch over level h.  From kBigRecon kTile2 tiles on (16 per
-// CU) it is 2 kTile2: four pixels per thread, a quarter of the blocks and of the re-read
-// footprint margins (batch of 64 streams: 464 -> 268 us per frame).  Below that a launch is
-// short and latency-bound and the one-pixel tile is faster (one 512 x 512 stream: 8.3 us
-// against 9.8).  Both give bitwise the same results.
-static constexpr int kBigRecon = 16 * 256;
+// Tile side of a pyramid (above = 0) or reconstruction (above = 1) launch over level h.  From
+// kBigLaunch kTile2 tiles on (16 per CU) it is 2 kTile2: four times the pixels per block, a
+// quarter of the blocks and of the re-read margins (reconstruction of a batch of 64 streams:
+// 464 -> 268 us per frame).  Below that a launch is short and latency-bound and the smaller
+// tile is faster (reconstruction of one 512 x 512 stream: 8.3 us against 9.8).  Both tiles
+// give bitwise the same results.
+static constexpr int kBigLaunch = 16 * 256;
 
-static int recon_tile(sf_ctx c, int level) {
-    const ElemArgs a = tile_args(c, level, 1, 0);
-    return a.blk[a.n] >= kBigRecon ? 2 * kTile2 : kTile2;
+static int big_tile(sf_ctx c, int level, int above) {
+    const ElemArgs a = tile_args(c, level, above, 0);
+    return a.blk[a.n] >= kBigLaunch ? 2 * kTile2 : kTile2;
 }
+
+static int recon_tile(sf_ctx c, int level) { return big_tile(c, level, 1); }
 
 extern "C" {
 
@@ -846,10 +849,11 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
     }
     // pyramid, finest to coarsest: one launch per two depths (d, d + 1) for all streams
     for (int h = 1; h < c->max_levels; h += 2) {
-        ElemArgs a = tile_args(c, h, 0, 0);
+        const int tile = big_tile(c, h, 0);
+        ElemArgs a = tile_args(c, h, 0, 0, tile);
         a.in = in;
         TimedLaunch t(c, 0);
-        HIP_TRY(c, launch_pyramid(c->storage, a, c->stream));
+        HIP_TRY(c, launch_pyramid(c->storage, tile, a, c->stream));
         t.done();
     }
     if (c->frames == 0) {

@@ -113,7 +113,8 @@ struct ElemArgs {
 };
 
 // kernel launchers (sflow_kernels.hip); `storage` is SF_FP32 or SF_FP16
-hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s);
+// tile: kTile2 or 2 kTile2 (the blocks in a.blk count tiles of that size)
+hipError_t launch_pyramid(int storage, int tile, const ElemArgs& a, hipStream_t s);
 hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds_bytes,
                        hipStream_t s);

@@ -833,22 +833,22 @@ __device__ __forceinline__ void pyr_sample(Load ld, int i, int j, int rows, int 
     r = den > 0.0f ? num / den : __int_as_float(0x7fc00000);
 }
 
-// Two pyramid levels per launch: the entry is level d (>= 1).  A block owns a kTile2 x kTile2
-// tile of level d and, if level d + 1 exists, the kTile2/2 x kTile2/2 tile of level d + 1
-// above it.  The level d - 1 pixels the tile reads (at most 2 (kTile2 + 3) + 3 per side) are
-// staged in LDS first, each loaded once with all of a thread's loads in flight together.
-// Phase 1 computes level d on the tile plus the rows and columns that level d + 1 reads (at
-// most kTile2 + 3 per side, one pixel per thread) into LDS, as stored (rounded to T), and writes
-// the tile's own pixels; phase 2 computes level d + 1 from LDS.  Every level-d pixel is written
-// by exactly one block.
-constexpr int kPyrPatch = kTile2 + 3;
-constexpr int kPyrSrc = 2 * kPyrPatch + 3;
+// Two pyramid levels per launch: the entry is level d (>= 1).  A block owns a TILE x TILE
+// tile of level d (TILE = 16, or 32 for launches large enough to fill the chip with the bigger
+// tiles) and, if level d + 1 exists, the TILE/2 x TILE/2 tile of level d + 1 above it.  The
+// level d - 1 pixels the tile reads (at most 2 (TILE + 3) + 3 per side) are staged in LDS
+// first, each loaded once with all of a thread's loads in flight together.  Phase 1 computes
+// level d on the tile plus the rows and columns that level d + 1 reads (at most TILE + 3 per
+// side) into LDS, as stored (rounded to T), and writes the tile's own pixels; phase 2 computes
+// level d + 1 from LDS.  Every level-d pixel is written by exactly one block.
 constexpr int kPyrThreads = 512;
-static_assert(kPyrPatch * kPyrPatch <= kPyrThreads, "one patch pixel per thread");
-template <typename T>
+template <typename T, int TILE>
 __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
-    constexpr int P = kPyrPatch, Q = kPyrSrc;
-    constexpr int NL = (Q * Q + kPyrThreads - 1) / kPyrThreads;
+    constexpr int P = TILE + 3, Q = 2 * P + 3;
+    constexpr int NL = (Q * Q + kPyrThreads - 1) / kPyrThreads;   // staged pixels per thread
+    constexpr int NP = (P * P + kPyrThreads - 1) / kPyrThreads;   // patch pixels per thread
+    constexpr int H2 = TILE / 2;
+    static_assert(H2 * H2 <= kPyrThreads, "one level d + 1 pixel per thread");
     __shared__ float pY[P][P + 1], pR[P][P + 1];
     __shared__ float sY[Q][Q + 1], sR[Q][Q + 1];
     int k, t;
@@ -862,16 +862,16 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     const int urows = U.rows, ucols = U.cols, upitch = U.pitch;
     T* const uYm = (T*)U.Ym;
     T* const uRm = (T*)U.Rm;
-    const int ntx = (D.cols + kTile2 - 1) / kTile2;
-    const int ti0 = (t / ntx) * kTile2, tj0 = (t % ntx) * kTile2;
+    const int ntx = (D.cols + TILE - 1) / TILE;
+    const int ti0 = (t / ntx) * TILE, tj0 = (t % ntx) * TILE;
     const bool two = D.parent >= 0;
-    int r0 = ti0, r1 = min(ti0 + kTile2, D.rows), q0 = tj0, q1 = min(tj0 + kTile2, D.cols);
+    int r0 = ti0, r1 = min(ti0 + TILE, D.rows), q0 = tj0, q1 = min(tj0 + TILE, D.cols);
     int a2 = 0, b2 = 0, c2 = 0, d2 = 0;
     if (two) {
         a2 = ti0 / 2;
-        b2 = min(a2 + kTile2 / 2, urows);
+        b2 = min(a2 + H2, urows);
         c2 = tj0 / 2;
-        d2 = min(c2 + kTile2 / 2, ucols);
+        d2 = min(c2 + H2, ucols);
         r0 = min(r0, max(2 * a2 - 2, 0));
         r1 = max(r1, min(2 * b2 + 1, D.rows));
         q0 = min(q0, max(2 * c2 - 2, 0));
@@ -906,26 +906,29 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
         }
     }
     __syncthreads();
-    if (p < nr * nc) {
-        const int li = p / nc, lj = p - li * nc;
+    auto from_src = [&](int ii, int jj, float& y, float& r) {
+        y = sY[ii - s0][jj - u0];
+        r = sR[ii - s0][jj - u0];
+    };
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const int q = p + m * kPyrThreads;
+        if (q >= nr * nc) continue;
+        const int li = q / nc, lj = q - li * nc;
         const int i = r0 + li, j = q0 + lj;
-        auto from_src = [&](int ii, int jj, float& y, float& r) {
-            y = sY[ii - s0][jj - u0];
-            r = sR[ii - s0][jj - u0];
-        };
         float y, r;
         pyr_sample(from_src, i, j, S.rows, S.cols, y, r);
         pY[li][lj] = rnd<T>(y);
         pR[li][lj] = rnd<T>(r);
-        if (i >= ti0 && i < ti0 + kTile2 && j >= tj0 && j < tj0 + kTile2) {
+        if (i >= ti0 && i < ti0 + TILE && j >= tj0 && j < tj0 + TILE) {
             stv((T*)D.Ym, (size_t)i * D.pitch + j, y);
             stv((T*)D.Rm, (size_t)i * D.pitch + j, r);
         }
     }
     if (!two) return;
     __syncthreads();
-    const int i = a2 + p / (kTile2 / 2), j = c2 + p % (kTile2 / 2);
-    if (p >= (kTile2 / 2) * (kTile2 / 2) || i >= b2 || j >= d2) return;
+    const int i = a2 + p / H2, j = c2 + p % H2;
+    if (p >= H2 * H2 || i >= b2 || j >= d2) return;
     auto from_lds = [&](int ii, int jj, float& y, float& r) {
         y = pY[ii - r0][jj - q0];
         r = pR[ii - r0][jj - q0];
@@ -1342,12 +1345,20 @@ hipError_t prepare_kernels(size_t max_lds_bytes) {
 
 static int elem_blocks(const ElemArgs& a) { return a.blk[a.n]; }
 
-hipError_t launch_pyramid(int storage, const ElemArgs& a, hipStream_t s) {
+hipError_t launch_pyramid(int storage, int tile, const ElemArgs& a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_pyramid<__half>, dim3(elem_blocks(a)), dim3(kPyrThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_pyramid<float>, dim3(elem_blocks(a)), dim3(kPyrThreads), 0, s, a);
+    const dim3 g(elem_blocks(a)), b(kPyrThreads);
+    if (tile == 2 * kTile2) {
+        if (storage == SF_FP16)
+            hipLaunchKernelGGL((k_pyramid<__half, 2 * kTile2>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_pyramid<float, 2 * kTile2>), g, b, 0, s, a);
+    } else {
+        if (storage == SF_FP16)
+            hipLaunchKernelGGL((k_pyramid<__half, kTile2>), g, b, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_pyramid<float, kTile2>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 
