@@ -27,8 +27,21 @@ def _random_frames(rng, R, C, n, nan_frac=0.05):
     return out
 
 
+def _close_rho(got, want, outliers):
+    """Inverse-depth state within float32 rounding; with outliers > 0, that fraction of pixels
+    may differ by up to 1e-3: where the two neighbours' flows are a near tie for the dominant
+    one (eq:dominant_b1, eq:dominant_b2), FP32 and FP64 can pick different neighbours, and the
+    transported inverse depth then differs by more than rounding at those pixels."""
+    if outliers == 0:
+        np.testing.assert_allclose(got, want, atol=2e-5, rtol=1e-4)
+        return
+    bad = ~np.isclose(got, want, atol=2e-5, rtol=1e-4, equal_nan=True)
+    assert bad.mean() <= outliers, bad.sum()
+    np.testing.assert_allclose(got, want, atol=1e-3)
+
+
 def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None, bar=FP32_EPE,
-         compare_state=True):
+         compare_state=True, rho_outliers=0.0):
     o, g = make_pair(R, C, H, mf, smooth, cam, storage=storage, read_flags=read_flags)
     dmu = o.grids[0].dmu
     worst = 0.0
@@ -47,7 +60,7 @@ def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None, ba
             assert dt_prev == dt
             for h in range(H):
                 np.testing.assert_allclose(st[h]["Y"], o.state[h]["Y"], atol=2e-6)
-                np.testing.assert_allclose(st[h]["rho"], o.state[h]["rho"], atol=2e-5, rtol=1e-4)
+                _close_rho(st[h]["rho"], o.state[h]["rho"], rho_outliers)
     g.close()
     return worst
 
@@ -82,6 +95,18 @@ def test_deep_pyramid():
     w = _run(frames, R, C, 6, 8.0, [2, 2, 2, 2, 1, 1], (120.0, 110.0, 64.2, 73.9),
              dts=[0.01] * 4)
     log("six levels worst mean EPE", w)
+
+
+def test_max_levels():
+    """The maximum of eight levels, down to a 2x2 coarsest level (130x150 -> ... -> 2x2): four
+    pyramid launches (the last of one level), reconstruction launches in pairs, levels smaller
+    than a tile's halo, against the oracle on every pixel."""
+    rng = np.random.default_rng(23)
+    R, C = 130, 150
+    frames = _random_frames(rng, R, C, 4)
+    w = _run(frames, R, C, 8, 8.0, [2, 2, 2, 1, 1, 1, 1, 1], (120.0, 115.0, 74.5, 64.5),
+             dts=[0.01, 0.01, 0.02, 0.02], rho_outliers=1e-3)
+    log("eight levels worst mean EPE", w)
 
 
 @pytest.mark.parametrize("storage", [0, 1])
