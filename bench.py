@@ -405,12 +405,14 @@ def main():
             "hbm_achieved_gbs": achieved_gbs,
             "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
             "frac_of_unpacked_fp32": achieved_tflops / FP32_UNPACKED_TFLOPS,
-            # share of every SIMD's issue cycles spent on VALU instructions over the launch
-            # (SQ_INSTS_VALU of the committed counters, 4 cycles per wave64 instruction, against
-            # 256 CUs x 4 SIMDs x 2.4 GHz x the live kernel time): the instructions the FLOP
-            # model does not count (halo recomputation, lane shifts, selects) included
-            "valu_issue_frac": (counters["valu"] * 4 / (256 * 4 * 2.4e9 * step_ms * 1e-3)
-                                if counters and counters["valu"] else None),
+            # VALU wave64 instructions retired per SIMD per 4 cycles over the launch
+            # (SQ_INSTS_VALU of the committed counters against 256 CUs x 4 SIMDs x 2.4 GHz x
+            # the live kernel time / 4), the instructions the FLOP model does not count (halo
+            # recomputation, lane shifts, selects) included.  A rate against a nominal one
+            # instruction per 4 cycles, not a utilisation: some instructions issue faster, and
+            # a long batched launch of this kernel measured 1.13 on it
+            "valu_rate_nominal": (counters["valu"] * 4 / (256 * 4 * 2.4e9 * step_ms * 1e-3)
+                                  if counters and counters["valu"] else None),
         },
         "kernel_us_per_frame": {k: v / max(1, n) * 1e3 * n / args.steps for k, v, n in
                                 zip(("pyramid", "level_step", "reconstruct"), r["kernel_ms"],
