@@ -65,7 +65,16 @@ def render_frames(seq, device):
     return Ys, Rs
 
 
-def run_gpu(wl_name, steps, warmup, storage=0):
+def tune_levels(rows, cols, levels, max_flow, smooth):
+    """The autotuner's description of one stream's levels."""
+    lv = []
+    for h in range(levels):
+        lv.append(dict(rows=rows, cols=cols, max_flow_px=max_flow, smooth=smooth[h], h=h))
+        rows, cols = (rows + 1) // 2, (cols + 1) // 2
+    return lv
+
+
+def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
     import torch
     from paper_2406_18031_amd import sflow
     from synth.workloads import workload
@@ -81,6 +90,13 @@ def run_gpu(wl_name, steps, warmup, storage=0):
     f = sflow.Filter(seq.rows, seq.cols, wl["levels"], wl["max_flow_px"], wl["smooth"],
                      cam.fx, cam.fy, cam.cx, cam.cy, storage=storage)
     out = torch.empty((3, seq.rows, seq.cols), dtype=torch.float32, device="cuda")
+    setting = None
+    if autotune:   # launch shape from the autotuner, then the stream restarts from frame 0
+        from paper_2406_18031_amd import tune
+        setting = tune.tune(f.ctx, lambda k: f.push(Ys[k % F], Rs[k % F], seq.dt),
+                            tune_levels(seq.rows, seq.cols, wl["levels"], wl["max_flow_px"],
+                                        wl["smooth"]))
+        sflow.sf_set_camera(f.ctx, cam.fx, cam.fy, cam.cx, cam.cy)
 
     def step(k):
         f.push(Ys[k % F], Rs[k % F], seq.dt)
@@ -105,7 +121,8 @@ def run_gpu(wl_name, steps, warmup, storage=0):
     sflow.sf_set_timing(f.ctx, False)
     final = f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
     f.close()
-    return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n, final=final)
+    return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n, final=final,
+                tuned=setting)
 
 
 def run_batched(n_streams, steps, warmup, storage=0, frames=6):
@@ -443,7 +460,7 @@ def main():
             print(f"[bench] batched {rb['storage']}: {rb['aggregate_frames_per_s']:.1f} "
                   f"stream-frames/s ({rb['mpix_per_s']:.0f} Mpix/s)", flush=True)
         rd = run_gpu("driving2048x1024", max(10, args.steps // 2), max(2, args.warmup // 2),
-                     storage=1)
+                     storage=1, autotune=True)
         ld = level_table(rd["seq"].rows, rd["seq"].cols, rd["wl"]["levels"], rd["wl"]["max_flow_px"],
                          rd["wl"]["smooth"])
         msd = rd["kernel_ms"][1] / max(1, rd["kernel_n"][1])   # per level-step launch
@@ -456,6 +473,7 @@ def main():
                                       for L in ld) / (msd * launches * 1e-3) / 1e9,
             "workload": "2048x1024, 4 levels, max flow 16 px (N=16/8/4/2), driving scene, "
                         "FP16 storage",
+            "tuned": {"pass_steps": rd["tuned"]["pass_steps"], "tiles": rd["tuned"]["tiles"]},
         }
         print(f"[bench] large 2048x1024 fp16: {forms['large_2048x1024_fp16']['frames_per_s']:.1f} "
               f"frames/s", flush=True)
