@@ -96,8 +96,8 @@ struct StepArgs {
 };
 
 // A launch of a per-pixel kernel over a list of entries: entry ent[k] owns blocks
-// [blk[k], blk[k+1]) of kElemBlock pixels each (of kTile2 x kTile2 tiles for the pyramid and
-// reconstruction kernels).
+// [blk[k], blk[k+1]) of kElemBlock pixels each (for the pyramid and reconstruction kernels: of
+// tiles of the side the launch is made with, kTile2 or 2 kTile2).
 struct ElemArgs {
     const LevelDev* lv;
     int n;
