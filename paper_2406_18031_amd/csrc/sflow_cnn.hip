@@ -65,6 +65,17 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     const int t = b - a.tblk[sgi];
     const int tiles_x = (cols + kConvTile - 1) / kConvTile;
     const int ty0 = (t / tiles_x) * kConvTile, tx0 = (t % tiles_x) * kConvTile;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int col = lane & 15;           // A row: pixel column within the tile; D column: channel
+    const int quad = lane >> 4;          // A/B k block: input channels 4 quad .. +3
+    // B: weight[tap][out j = lane % 16][in 4 (lane / 16) .. +3], loaded first so that its
+    // latency overlaps the patch loads'
+    s4 bv[9];
+#pragma unroll
+    for (int tp = 0; tp < 9; ++tp)
+        bv[tp] = unpack4(*(const uint2*)(a.w + ((size_t)tp * 16 + col) * 16 + 4 * quad));
+    const float bias = a.bias ? a.bias[col] : 0.0f;
     {   // every load of the patch in flight together (addresses outside the image read the
         // first pixel and are zeroed), then the LDS stores
         constexpr int NQ = kConvPatch * kConvPatch * 4, NL = (NQ + 255) / 256;
@@ -95,16 +106,6 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
             patch[q] = v;
         }
     }
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int col = lane & 15;           // A row: pixel column within the tile; D column: channel
-    const int quad = lane >> 4;          // A/B k block: input channels 4 quad .. +3
-    // B: weight[tap][out j = lane % 16][in 4 (lane / 16) .. +3]
-    s4 bv[9];
-#pragma unroll
-    for (int tp = 0; tp < 9; ++tp)
-        bv[tp] = unpack4(*(const uint2*)(a.w + ((size_t)tp * 16 + col) * 16 + 4 * quad));
-    const float bias = a.bias ? a.bias[col] : 0.0f;
     __syncthreads();
     // results go to an LDS copy of the output tile first, then every thread writes one pixel
     // whole (two 16-byte stores, or three channel planes), instead of 2-byte stores per lane
