@@ -44,3 +44,59 @@ def make_pair(R, C, H, mf, smooth, cam, alpha=None, storage=0, read_flags=0):
     g = sflow.Filter(R, C, H, mf, smooth, *cam, alpha=alpha, storage=storage,
                      read_flags=read_flags)
     return o, g
+
+
+# Parity bars per frame at the finest level, in pixels: the mean over the image and its 99th
+# percentile at most the endpoint-error bound (1e-3 px for FP32 storage, 2e-2 px for FP16), the
+# largest pixel at most 10x that.  The allowance for single pixels is for near ties of the
+# dominant flow (eq:dominant_b1, eq:dominant_b2): where the two neighbours' flow components are
+# equal to within rounding, FP32 and FP64 may pick different neighbours for a step.
+BARS = {0: (1e-3, 1e-2), 1: (2e-2, 2e-1)}
+
+
+def _stats(e):
+    e = np.asarray(e, np.float64)
+    return {"mean": float(e.mean()), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
+
+
+def check_bar(e, storage, what):
+    bar, maxbar = BARS[storage]
+    assert e["mean"] <= bar and e["p99"] <= bar and e["max"] <= maxbar, (what, e)
+
+
+def compare_outputs(g, o, storage, what="", rho_outliers=0.0):
+    """Every sf_get_flow kind of the GPU filter g against the oracle o's flow() after the same
+    frames: structure flow in rad/frame and rad/s (endpoint error), tangent flow (the 2-vector's
+    error in pixels, eq:tangent_flow), normal flow (pixels, eq:normal_flow) and the inverse
+    depth (within the stored precision's rounding).  Returns the endpoint-error statistics of
+    the rad/frame flow."""
+    from paper_2406_18031_amd import sflow
+    dmu = o.grids[0].dmu
+
+    def kind(k):
+        return g.flow(k).cpu().numpy().astype(np.float64)
+
+    e = _stats(np.sqrt(np.sum((kind(sflow.SF_FLOW_W_FRAME).transpose(1, 2, 0)
+                               - o.flow("w_frame")) ** 2, -1)) / dmu)
+    check_bar(e, storage, (what, "w_frame"))
+    dt = o.dt_prev
+    es = _stats(np.sqrt(np.sum((kind(sflow.SF_FLOW_W_RAD_S).transpose(1, 2, 0)
+                                - o.flow("w_rad_s")) ** 2, -1)) * dt / dmu)
+    check_bar(es, storage, (what, "w_rad_s"))
+    et = _stats(np.sqrt(np.sum((kind(sflow.SF_FLOW_TANGENT_PX).transpose(1, 2, 0)
+                                - o.flow("tangent_px")) ** 2, -1)))
+    check_bar(et, storage, (what, "tangent_px"))
+    en = _stats(np.abs(kind(sflow.SF_FLOW_NORMAL_PX)[0] - o.flow("normal_px")))
+    check_bar(en, storage, (what, "normal_px"))
+    r = kind(sflow.SF_FLOW_RHO)[0]
+    want = o.flow("rho")
+    atol, rtol = (2e-5, 1e-4) if storage == 0 else (1e-3, 5e-3)
+    bad = ~np.isclose(r, want, atol=atol, rtol=rtol)
+    assert bad.mean() <= rho_outliers, (what, "rho", int(bad.sum()),
+                                        float(np.abs(r - want).max()))
+    np.testing.assert_allclose(r, want, atol=max(atol, 1e-3 if rho_outliers else 0.0))
+    log(f"    {what}: w {e['mean']:.2e}/{e['p99']:.2e}/{e['max']:.2e} "
+        f"tangent {et['mean']:.2e}/{et['p99']:.2e}/{et['max']:.2e} "
+        f"normal {en['mean']:.2e}/{en['p99']:.2e}/{en['max']:.2e} (mean/p99/max px) "
+        f"rho max {float(np.abs(r - want).max()):.2e}")
+    return e

@@ -3,7 +3,7 @@ gives bitwise the result of the same stream run alone, and matches the oracle.""
 import numpy as np
 import pytest
 
-from gpu_helpers import epe_px, log, to_dev
+from gpu_helpers import check_bar, epe_px, log, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_batch_matches_single_streams_and_oracle():
             assert np.array_equal(wb, ws), (k, s)
             e = epe_px(wb.transpose(1, 2, 0) * dts[s][k], oracles[s].flow("w_frame"),
                        oracles[s].grids[0].dmu)
-            assert e["mean"] <= 1e-3, (k, s, e)
+            check_bar(e, 0, ("frame", k, "stream", s))
     batch.close()
     for f in singles:
         f.close()
@@ -236,7 +236,6 @@ def test_stream_mix_workload(storage):
     oracles = {s: Oracle(specs[s]["rows"], specs[s]["cols"], specs[s]["levels"],
                          specs[s]["max_flow_px"], specs[s]["smooth"], *specs[s]["camera"])
                for s in checked}
-    bar = 1e-3 if storage == 0 else 2e-2
     for k in range(nfr):
         log(f"  frame {k}")
         push(k)
@@ -253,8 +252,9 @@ def test_stream_mix_workload(storage):
             o.push(rounded(Y, storage), rounded(rho, storage), dt)
             e = epe_px(got[s].cpu().numpy().transpose(1, 2, 0), o.flow("w_frame"),
                        o.grids[0].dmu)
-            log(f"    stream {s} ({sizes[s]}^2) mean EPE {e['mean']:.2e} max {e['max']:.2e}")
-            assert e["mean"] <= bar, (k, s, e)
+            log(f"    stream {s} ({sizes[s]}^2) EPE mean {e['mean']:.2e} p99 {e['p99']:.2e} "
+                f"max {e['max']:.2e}")
+            check_bar(e, storage, ("frame", k, "stream", s))
     batch.close()
     for f in singles:
         f.close()

@@ -1,18 +1,20 @@
 """GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
 
-Bar (per frame, finest level): mean endpoint error |w_gpu - w_oracle| / dmu at most
-1e-3 px in FP32 storage and 2e-2 px in FP16 storage; state planes (rho, Yhat) within the
-float32 rounding of their values.
+Bar (per frame, finest level, every output kind of sf_get_flow): endpoint error
+|w_gpu - w_oracle| / dmu with its mean and 99th percentile at most 1e-3 px in FP32 storage and
+2e-2 px in FP16 storage and its largest pixel at most 10x that; the tangent and normal flows
+to the same bars in pixels; inverse depth and the state planes (rho, Yhat) within the rounding
+of their stored values.
 """
 import numpy as np
 import pytest
 
-from gpu_helpers import epe_px, gpu_flow_frame, log, make_pair, rounded, to_dev
+from gpu_helpers import BARS, check_bar, compare_outputs, epe_px, gpu_flow_frame, log, make_pair, rounded, to_dev
 
 pytestmark = pytest.mark.gpu
 
-FP32_EPE = 1e-3
-FP16_EPE = 2e-2
+FP32_EPE = BARS[0][0]
+FP16_EPE = BARS[1][0]
 
 
 def _random_frames(rng, R, C, n, nan_frac=0.05):
@@ -40,10 +42,9 @@ def _close_rho(got, want, outliers):
     np.testing.assert_allclose(got, want, atol=1e-3)
 
 
-def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None, bar=FP32_EPE,
+def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None,
          compare_state=True, rho_outliers=0.0):
     o, g = make_pair(R, C, H, mf, smooth, cam, storage=storage, read_flags=read_flags)
-    dmu = o.grids[0].dmu
     worst = 0.0
     for k, (Y, rho) in enumerate(frames):
         dt = 1.0 if dts is None else dts[k]
@@ -52,9 +53,8 @@ def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None, ba
         log(f"  frame {k} {R}x{C} H={H} storage={storage} flags={read_flags}")
         g.push(to_dev(Y, dtype), to_dev(rho, dtype), dt)
         o.push(Yr, rr, dt)
-        e = epe_px(gpu_flow_frame(g), o.flow("w_frame"), dmu)
+        e = compare_outputs(g, o, storage, f"frame {k}", rho_outliers=rho_outliers)
         worst = max(worst, e["mean"])
-        assert e["mean"] <= bar, (k, e)
         if compare_state and storage == 0:
             st, dt_prev, _ = g.get_state()
             assert dt_prev == dt
@@ -210,7 +210,7 @@ def test_fp16_storage_plane64():
     Y, rho, _ = render_sequence(seq)
     c = seq.camera
     w = _run(list(zip(Y, rho)), 64, 64, 1, wl["max_flow_px"], wl["smooth"],
-             (c.fx, c.fy, c.cx, c.cy), storage=1, dts=[seq.dt] * len(Y), bar=FP16_EPE)
+             (c.fx, c.fy, c.cx, c.cy), storage=1, dts=[seq.dt] * len(Y))
     log("plane64 fp16 worst mean EPE", w)
 
 
@@ -230,12 +230,13 @@ def _workload_frames(name, n):
 @pytest.mark.parametrize("storage", [0, 1])
 def test_boxes512_workload(storage):
     """The bench's 512x512 three-level workload at full size, in the bench's launch
-    configuration: every pixel of the first frames against the oracle."""
-    wl, seq, frames = _workload_frames("boxes512", 4)
+    configuration: every pixel of every output kind over the first 20 frames (19 updates
+    through the recurrence) against the oracle."""
+    n = 20
+    wl, seq, frames = _workload_frames("boxes512", n)
     c = seq.camera
-    bar = FP32_EPE if storage == 0 else FP16_EPE
     w = _run(frames, seq.rows, seq.cols, wl["levels"], wl["max_flow_px"], wl["smooth"],
-             (c.fx, c.fy, c.cx, c.cy), storage=storage, dts=[seq.dt] * 4, bar=bar)
+             (c.fx, c.fy, c.cx, c.cy), storage=storage, dts=[seq.dt] * n)
     log("boxes512 storage", storage, "worst mean EPE", w)
 
 
@@ -271,6 +272,6 @@ def test_driving_2048x1024_fp16():
         wg = gpu_flow_frame(g)[y0 + m:y0 + n - m, x0 + m:x0 + n - m]
         wo = o.flow("w_frame")[m:n - m, m:n - m]
         e = epe_px(wg, wo, o.grids[0].dmu[m:n - m, m:n - m])
-        log(f"    mean EPE {e['mean']:.2e} max {e['max']:.2e}")
-        assert e["mean"] <= FP16_EPE, (k, e)
+        log(f"    EPE mean {e['mean']:.2e} p99 {e['p99']:.2e} max {e['max']:.2e}")
+        check_bar(e, 1, ("2048x1024 crop", k))
     g.close()
