@@ -22,7 +22,12 @@
  *    call that consumed it.  Calls return without waiting for the device, except
  *    sf_get_state / sf_set_state, which synchronise the stream.
  *  - Every call validates all arguments before it enqueues anything: a call that returns an
- *    error leaves the context unchanged (except the sticky SF_ERR_HIP below).
+ *    error leaves the context unchanged (except the sticky SF_ERR_HIP below).  Calls that
+ *    allocate device memory (sf_create*, sf_set_camera*, sf_set_tile, sf_set_pass_steps,
+ *    sf_net_create) allocate before they release anything, so SF_ERR_OOM leaves the context
+ *    as it was too.  For tests, the environment variable SFLOW_FAIL_ALLOC=n makes the n-th
+ *    device allocation, counted from the moment the variable took its current value, fail
+ *    with SF_ERR_OOM.
  *  - A context may be used from one host thread at a time.
  *  - Return values are sf_status codes; nothing throws or aborts across the ABI.
  *    sf_last_error(ctx) gives a text for the last failure on that context.
@@ -224,7 +229,8 @@ sf_status sf_kernel_times(sf_ctx ctx, double* ms3, int64_t* launches3, int32_t r
  * G1 (aY.c)^2 + G2 (aR.c)^2 + gamma_3 |c|^2 (in pixel units, the cost increase a step c away
  * from the minimum x_ls), exceeds `threshold` or is not finite (a "fallback": the plain
  * flow).  A threshold < 0 makes every pixel fall back, which gives exactly the plain
- * update.  sf_get_state / sf_set_state carry the state only, not the correction.
+ * update.  sf_get_state / sf_set_state carry the state only, not the correction;
+ * sf_set_state clears the stream's correction, so the flow read back is the state's.
  *
  * The parameters are FP32, SF_LEARNED_PARAMS values: per layer l = 0..3 the weights
  * W[3][3][cin][cout] (tap row dy+1, tap column dx+1, input channel, output channel;
@@ -241,7 +247,8 @@ sf_status sf_learned_stats(sf_ctx ctx, int64_t* fallbacks, int64_t* pixels, int3
  * SF_UPDATE_INPUT_PLANES float32 planes of rows x cols to the device pointer out: the network
  * inputs (9, as the network reads them: rounded to BF16), x0 (3), x_ls (3), S(x_ls) (3), the
  * parent's reconstructed flow (3; 0 at a top level) and dmu (1).  Flows are in rad/frame, so the network output that reaches a flow w is
- * (w - parent - S(x_ls)) / dmu.  SF_ERR_STATE before the second frame. */
+ * (w - parent - S(x_ls)) / dmu.  SF_ERR_STATE until an update has run after the camera or
+ * the stream's state was last set. */
 sf_status sf_get_update_inputs(sf_ctx ctx, int32_t stream, float* out);
 
 /* ---- training the learned update's network --------------------------------------------------

@@ -14,7 +14,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,6 +33,7 @@ struct StreamInfo {
     int e0 = 0;                    // first entry of the stream (its finest level)
     double cam[4] = {0, 0, 0, 0};
     double dt_prev = 0.0;
+    bool update_ran = false;       // an update has run since the camera or the state was set
 };
 
 struct sf_ctx_s {
@@ -87,6 +91,29 @@ struct sf_ctx_s {
 };
 
 static std::string g_create_error;
+
+// Every device allocation of the library goes through dev_malloc.  For testing the error
+// paths, SFLOW_FAIL_ALLOC=n in the environment makes the n-th allocation counted from the
+// moment the variable took its current value fail as if the device were out of memory.
+hipError_t sflow::dev_malloc(void** p, size_t bytes) {
+    static std::mutex mu;
+    static std::string seen;
+    static long count = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        const char* v = getenv("SFLOW_FAIL_ALLOC");
+        const std::string cur = v ? v : "";
+        if (cur != seen) {
+            seen = cur;
+            count = 0;
+        }
+        if (!cur.empty() && ++count == strtol(cur.c_str(), nullptr, 10)) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc(p, bytes);
+}
 
 static sf_status fail(sf_ctx c, sf_status s, const char* fmt, ...) {
     char buf[512];
@@ -213,28 +240,37 @@ static void choose_tiles(sf_ctx c, LevelDev& L) {
     L.tiles_y = (L.rows + th - 1) / th;
 }
 
-// Pass entries and step launches.  A level with P passes runs pass i in launch
-// Pmax - P + i, so every level's last pass (update, smoothing, store) is in the last launch.
-// Returns the bytes of FP32 intermediate fields the split levels need.
-static size_t layout_blocks(sf_ctx c) {
+// Pass entries and step launches, computed into `out` from the context's levels, pass length
+// and tile choices (the context itself is not changed).  A level with P passes runs pass i in
+// launch Pmax - P + i, so every level's last pass (update, smoothing, store) is in the last
+// launch.  `mid` is the base of the FP32 intermediate fields of split levels (NULL: not yet
+// allocated; the pass entries then hold NULL for them).  Returns the bytes of those fields.
+struct Layout {
+    std::vector<LevelDev> lv;                       // the levels with their last pass's tiles
+    std::vector<LevelDev> sv;                       // pass entries, launch by launch
+    std::vector<sf_ctx_s::StepLaunch> launches;
+};
+
+static size_t layout_blocks(sf_ctx c, float* mid, Layout& out) {
+    out.lv = c->lv;
+    out.sv.clear();
+    out.launches.clear();
     int pmax = 1;
-    for (auto& L : c->lv) pmax = std::max(pmax, npasses(L.N, c->pass_steps));
-    c->sv.clear();
-    c->step_launches.clear();
+    for (auto& L : out.lv) pmax = std::max(pmax, npasses(L.N, c->pass_steps));
     size_t mid_off = 0;
-    std::vector<size_t> mid_at(c->lv.size(), 0);
-    for (size_t e = 0; e < c->lv.size(); ++e) {
-        const LevelDev& L = c->lv[e];
+    std::vector<size_t> mid_at(out.lv.size(), 0);
+    for (size_t e = 0; e < out.lv.size(); ++e) {
+        const LevelDev& L = out.lv[e];
         if (npasses(L.N, c->pass_steps) > 1) {
             mid_at[e] = mid_off;
             mid_off += 2 * 8 * ((size_t)L.rows * L.pitch * sizeof(float) + 255) / 256 * 256;
         }
     }
     for (int k = 0; k < pmax; ++k) {
-        sf_ctx_s::StepLaunch sl{(int)c->sv.size(), 0, 0};
+        sf_ctx_s::StepLaunch sl{(int)out.sv.size(), 0, 0};
         int b = 0;
-        for (size_t e = 0; e < c->lv.size(); ++e) {
-            LevelDev& L = c->lv[e];
+        for (size_t e = 0; e < out.lv.size(); ++e) {
+            LevelDev& L = out.lv[e];
             const int P = npasses(L.N, c->pass_steps);
             const int i = k - (pmax - P);
             if (i < 0) continue;
@@ -247,8 +283,8 @@ static size_t layout_blocks(sf_ctx c) {
             for (int f = 0; f < 8; ++f) {
                 S.mid_in[f] = nullptr;
                 S.mid_out[f] = nullptr;
-                if (P > 1 && c->mid) {
-                    float* base = (float*)((char*)c->mid + mid_at[e]);
+                if (P > 1 && mid) {
+                    float* base = (float*)((char*)mid + mid_at[e]);
                     if (!S.pass_first)
                         S.mid_in[f] = (float*)((char*)base + (((i - 1) & 1) * 8 + f) * plane);
                     if (!S.pass_last)
@@ -262,13 +298,12 @@ static size_t layout_blocks(sf_ctx c) {
                 L.tw = S.tw; L.th = S.th; L.tiles_x = S.tiles_x; L.tiles_y = S.tiles_y;
                 L.halo = S.halo;
             }
-            c->sv.push_back(S);
+            out.sv.push_back(S);
             ++sl.n;
         }
         sl.nblocks = b;
-        c->step_launches.push_back(sl);
+        out.launches.push_back(sl);
     }
-    c->lds_bytes = kLdsBytes;
     return mid_off;
 }
 
@@ -387,7 +422,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         }
     }
     total += align + sizeof(LevelDev) * (ctx->lv.size() + kLevelPad);   // zeroed padding
-    hipError_t e = hipMalloc((void**)&ctx->arena, total);
+    hipError_t e = dev_malloc((void**)&ctx->arena, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
@@ -430,7 +465,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         size_t act_bytes = (size_t)b * 16 * sizeof(uint16_t);
         size_t need = lb_bytes + 3 * act_bytes + 2 * 4 * 9 * 256 * sizeof(uint16_t) +
                       4 * 16 * sizeof(float) + kCnnParams * sizeof(float) + 64 + 6 * 256;
-        hipError_t e2 = hipMalloc((void**)&ctx->lbuf, need);
+        hipError_t e2 = dev_malloc((void**)&ctx->lbuf, need);
         if (e2 != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(ctx->arena);
@@ -487,40 +522,51 @@ sf_status sf_stream_count(sf_ctx c, int32_t* n) {
     return SF_OK;
 }
 
+// Lays the levels out again (after a change of cameras, tiles or pass length) and uploads the
+// tables.  New device buffers are allocated before the old ones are released, and the context
+// takes the new layout only once every allocation has succeeded, so that an allocation
+// failure (SF_ERR_OOM) leaves the context as it was.  Set-up work, not per frame.
 static sf_status upload_levels(sf_ctx c) {
-    const size_t need = layout_blocks(c);
-    if (need > c->mid_bytes || c->sv.size() > c->sv_cap) {
-        // (re)allocate the intermediate fields and the pass table, then lay out again with the
-        // new addresses; this is set-up work (camera, tiles, pass length), not per frame
+    Layout nl;
+    const size_t need = layout_blocks(c, c->mid, nl);
+    float* new_mid = nullptr;
+    LevelDev* new_sv = nullptr;
+    if (need > c->mid_bytes) {
+        hipError_t e = dev_malloc((void**)&new_mid, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                        "hipMalloc of %zu bytes for split predictions failed", need);
+        }
+    }
+    if (nl.sv.size() > c->sv_cap) {
+        hipError_t e = dev_malloc((void**)&new_sv, sizeof(LevelDev) * nl.sv.size());
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (new_mid) (void)hipFree(new_mid);
+            return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                        "hipMalloc of the pass table failed");
+        }
+    }
+    if (new_mid || new_sv) {
+        // the old buffers may still be read by enqueued work
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        if (need > c->mid_bytes) {
+        if (new_mid) {
             if (c->mid) HIP_TRY(c, hipFree(c->mid));
-            c->mid = nullptr;
-            c->mid_bytes = 0;
-            hipError_t e = hipMalloc((void**)&c->mid, need);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                c->mid = nullptr;
-                return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
-                            "hipMalloc of %zu bytes for split predictions failed", need);
-            }
+            c->mid = new_mid;
             c->mid_bytes = need;
         }
-        if (c->sv.size() > c->sv_cap) {
+        if (new_sv) {
             if (c->sv_dev) HIP_TRY(c, hipFree(c->sv_dev));
-            c->sv_dev = nullptr;
-            c->sv_cap = 0;
-            hipError_t e = hipMalloc((void**)&c->sv_dev, sizeof(LevelDev) * c->sv.size());
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                c->sv_dev = nullptr;
-                return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
-                            "hipMalloc of the pass table failed");
-            }
-            c->sv_cap = c->sv.size();
+            c->sv_dev = new_sv;
+            c->sv_cap = nl.sv.size();
         }
-        layout_blocks(c);
+        layout_blocks(c, c->mid, nl);   // with the new addresses
     }
+    c->lv = std::move(nl.lv);
+    c->sv = std::move(nl.sv);
+    c->step_launches = std::move(nl.launches);
+    c->lds_bytes = kLdsBytes;
     HIP_TRY(c, prepare_kernels(c->lds_bytes));
     HIP_TRY(c, hipMemcpyAsync(c->lv_dev, c->lv.data(), sizeof(LevelDev) * c->lv.size(),
                               hipMemcpyHostToDevice, c->stream));
@@ -541,6 +587,8 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
             return fail(c, SF_ERR_INVALID_ARG,
                         "camera %d: fx, fy must be finite and > 0, cx, cy finite", s);
     }
+    const std::vector<LevelDev> old_lv = c->lv;
+    const std::vector<StreamInfo> old_st = c->st;
     for (int s = 0; s < c->S; ++s) {
         StreamInfo& si = c->st[s];
         const sf_camera* cam = &cams[s];
@@ -569,10 +617,17 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
             L.qscale = (float)(1.0 / dmu0);   // half storage keeps flow in pixels per frame
         }
         si.dt_prev = 0.0;
+        si.update_ran = false;
+    }
+    sf_status s2 = upload_levels(c);
+    if (s2 != SF_OK) {
+        if (!c->hip_failed) {   // nothing was uploaded: the context stays as it was
+            c->lv = old_lv;
+            c->st = old_st;
+        }
+        return s2;
     }
     c->recon_pending = false;   // the state restarts
-    sf_status s2 = upload_levels(c);
-    if (s2 != SF_OK) return s2;
     c->camera = true;
     c->frames = 0;
     c->parity = 0;
@@ -604,9 +659,17 @@ sf_status sf_set_tile(sf_ctx c, int32_t level, int32_t tw, int32_t th) {
     }
     st = flush_recon(c);
     if (st != SF_OK) return st;
+    const int old_tw = c->user_tw[h], old_th = c->user_th[h];
     c->user_tw[h] = tw;
     c->user_th[h] = th;
-    if (c->camera) return upload_levels(c);
+    if (c->camera) {
+        sf_status s2 = upload_levels(c);
+        if (s2 != SF_OK) {
+            c->user_tw[h] = old_tw;
+            c->user_th[h] = old_th;
+            return s2;
+        }
+    }
     return SF_OK;
 }
 
@@ -808,7 +871,8 @@ sf_status sf_get_update_inputs(sf_ctx c, int32_t stream, float* out) {
     if (!c->learned) return fail(c, SF_ERR_STATE, "not a learned context");
     if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
     if (!is_device_ptr(out)) return fail(c, SF_ERR_INVALID_ARG, "out must be a device pointer");
-    if (c->frames < 2) return fail(c, SF_ERR_STATE, "no update has run yet");
+    if (c->frames < 2 || !c->st[stream].update_ran)
+        return fail(c, SF_ERR_STATE, "no update has run since the camera or the state was set");
     st = flush_recon(c);
     if (st != SF_OK) return st;
     ElemArgs a{};
@@ -891,6 +955,7 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         }
         c->recon_pending = c->max_levels >= 2;
         c->parity = q;
+        for (int s = 0; s < c->S; ++s) c->st[s].update_ran = true;
     }
     for (int s = 0; s < c->S; ++s) c->st[s].dt_prev = dt[s];
     c->frames += 1;
@@ -1181,6 +1246,17 @@ sf_status sf_set_state_stream(sf_ctx c, int32_t stream, const void* host_blob, s
     memcpy(tmp.data(), (const char*)host_blob + sizeof hd, bytes - sizeof hd);
     sf_status s2 = transfer_state(c, stream, false, tmp.data());
     if (s2 != SF_OK) return s2;
+    si.update_ran = false;
+    if (c->learned) {
+        // the learned correction of the output belongs to the frame before the new state:
+        // clear it, as the first frame does, so that the flow read back is the state's
+        const LevelDev& L = c->lv[si.e0];
+        const size_t P = (size_t)c->segs.total;
+        for (int k = 0; k < 3; ++k)
+            HIP_TRY(c, hipMemsetAsync(c->lbuf + (size_t)(kLearnCorr + k) * P + L.lbase, 0,
+                                      (size_t)L.rows * L.cols * sizeof(float), c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     if (c->S == 1) c->frames = std::max<int64_t>(1, hd.frames);
     si.dt_prev = hd.dt_prev;
     return SF_OK;

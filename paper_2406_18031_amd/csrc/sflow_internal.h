@@ -112,6 +112,11 @@ struct ElemArgs {
     FrameInputs in;
 };
 
+// Device allocation of the library (hipMalloc, with a failure-injection hook for tests: the
+// environment variable SFLOW_FAIL_ALLOC=n fails the n-th allocation counted from the moment
+// the variable took its current value).
+hipError_t dev_malloc(void** p, size_t bytes);
+
 // kernel launchers (sflow_kernels.hip); `storage` is SF_FP32 or SF_FP16
 // tile: kTile2 or 2 kTile2 (the blocks in a.blk count tiles of that size)
 hipError_t launch_pyramid(int storage, int tile, const ElemArgs& a, hipStream_t s);

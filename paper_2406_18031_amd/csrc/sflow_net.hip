@@ -170,7 +170,7 @@ sf_status sf_net_create(const int32_t* rows, const int32_t* cols, int32_t n_imag
         256};                                                             // loss
     size_t total = 0;
     for (size_t s : sizes) total += al(s);
-    hipError_t e = hipMalloc((void**)&n->mem, total);
+    hipError_t e = dev_malloc((void**)&n->mem, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete n;

@@ -110,3 +110,83 @@ def test_state_round_trip(sf):
     assert np.array_equal(a.flow().cpu().numpy(), b.flow().cpu().numpy())
     a.close()
     b.close()
+
+
+def _with_failing_alloc(n, fn, *a):
+    """Run fn with the n-th device allocation failing (SFLOW_FAIL_ALLOC); return its status."""
+    import os
+    os.environ["SFLOW_FAIL_ALLOC"] = str(n)
+    try:
+        return _code(fn, *a)
+    finally:
+        del os.environ["SFLOW_FAIL_ALLOC"]
+
+
+def test_allocation_failure_leaves_the_context_unchanged(sf):
+    """An allocation failure in a set-up call (creation, camera, pass length, tile) returns
+    SF_ERR_OOM and leaves the context as it was: the next pushes are bitwise those of a
+    context that never saw the failed call."""
+    log("allocation failure injection")
+    cfg = sf.make_config(48, 56, 2, 6.0, [2, 2])
+    cam = (50.0, 50.0, 27.5, 23.5)
+    assert _with_failing_alloc(1, sf.sf_create, cfg) == sf.SF_ERR_OOM
+    rng = np.random.default_rng(8)
+    frames = [(to_dev(rng.random((48, 56))), to_dev(0.2 + rng.random((48, 56)))) for _ in range(6)]
+    ref = sf.Filter(48, 56, 2, 6.0, [2, 2], *cam)
+    # a camera whose upload fails: no camera, pushes refused; then a camera that succeeds
+    ctx = sf.sf_create(cfg)
+    assert _with_failing_alloc(1, sf.sf_set_camera, ctx, *cam) == sf.SF_ERR_OOM
+    assert _code(sf.sf_push_frame, ctx, frames[0][0], frames[0][1], 0.01) == sf.SF_ERR_STATE
+    sf.sf_set_camera(ctx, *cam)
+    for k, (Y, r) in enumerate(frames):
+        if k == 2:
+            # pass length 2 splits the 6-step level: the split fields (allocation 1) or the
+            # larger pass table (allocation 2) cannot be allocated
+            assert _with_failing_alloc(1, sf.sf_set_pass_steps, ctx, 2) == sf.SF_ERR_OOM
+            assert _with_failing_alloc(2, sf.sf_set_pass_steps, ctx, 2) == sf.SF_ERR_OOM
+        if k == 3:   # a tile change that needs no allocation still goes through
+            sf.sf_set_tile(ctx, 1, 20, 20)
+            sf.sf_set_tile(ctx, 1, 0, 0)
+        sf.sf_push_frame(ctx, Y, r, 0.01)
+        ref.push(Y, r, 0.01)
+        out = ref.flow().cpu().numpy()
+        got = torch_flow(sf, ctx, 48, 56)
+        assert np.array_equal(got, out), k
+    # the context still takes the change once memory is there
+    sf.sf_set_pass_steps(ctx, 2)
+    sf.sf_destroy(ctx)
+    ref.close()
+
+
+def torch_flow(sf, ctx, R, C):
+    import torch
+    out = torch.empty((3, R, C), dtype=torch.float32, device="cuda")
+    sf.sf_get_flow(ctx, sf.SF_FLOW_W_FRAME, out)
+    return out.cpu().numpy()
+
+
+def test_learned_state_set_clears_the_correction(sf):
+    """On a learned context, setting a state clears the output correction of the frame before
+    it, so the flow read back is the state's, and the update inputs are refused until a push
+    has run an update."""
+    import torch
+    from paper_2406_18031_amd import learned
+    log("learned context: set_state")
+    rng = np.random.default_rng(9)
+    frames = [(to_dev(rng.random((40, 48))), to_dev(0.2 + rng.random((40, 48)))) for _ in range(4)]
+    f = sf.Filter(40, 48, 2, 3.0, [2, 2], 45.0, 45.0, 23.5, 19.5, update=sf.SF_UPDATE_LEARNED)
+    f.set_learned(learned.init_params(3, last_scale=1.0), float("inf"))
+    for Y, r in frames[:3]:
+        f.push(Y, r, 0.01)
+    before = f.flow().cpu().numpy()
+    blob = sf.sf_get_state(f.ctx)
+    st, _, _ = sf.unpack_state(blob, 40, 48, 2)
+    w_state = st[0]["w"].transpose(2, 0, 1)
+    assert np.abs(before - w_state).max() > 0      # the network corrects the output
+    sf.sf_set_state(f.ctx, blob)
+    np.testing.assert_array_equal(f.flow().cpu().numpy(), w_state.astype(np.float32))
+    out = torch.empty((sf.SF_UPDATE_INPUT_PLANES, 40, 48), device="cuda")
+    assert _code(sf.sf_get_update_inputs, f.ctx, 0, out) == sf.SF_ERR_STATE
+    f.push(*frames[3], 0.01)
+    sf.sf_get_update_inputs(f.ctx, 0, out)
+    f.close()
