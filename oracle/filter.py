@@ -17,6 +17,10 @@ push(Y, rho, dt) for frame k+1:
   S7  inverse-depth update                                   (update.py)
   S8  reconstruction w_h = up(w_{h+1}) + dw_h, h = H-1..1     (pyramid.py)
   S9  Yhat_h <- brightness model of the new frame
+With the camera's angular velocity Omega (rad/s) and linear acceleration a (m/s^2), both in
+the camera frame and taken as constant between the two frames (Section "Structure Flow"),
+push(..., omega, acc) keeps the inertial source terms that the paper drops by eq:assumption
+(predict.py): Omega dt and a dt^2 in the filter's time unit.
 The first frame only initialises: w = dw = 0, rho = measured rho (0 where missing),
 Yhat from the frame.  dt (seconds) only converts the output to rad/s: the scheme runs in
 frames.  When dt changes between frames, w and dw are rescaled by dt_new/dt_old so that
@@ -62,7 +66,7 @@ class Filter:
             rhos.append(pyramid.downsample_valid(rhos[-1]))
         return Ys, rhos
 
-    def push(self, Y, rho, dt: float):
+    def push(self, Y, rho, dt: float, omega=None, acc=None):
         Y = np.asarray(Y, dtype=np.float64)
         rho = np.asarray(rho, dtype=np.float64)
         if Y.shape != (self.rows, self.cols) or rho.shape != (self.rows, self.cols):
@@ -91,6 +95,11 @@ class Filter:
                 st["w"] = st["w"] * c
                 if "dw" in st:
                     st["dw"] = st["dw"] * c
+        imu = None
+        if omega is not None or acc is not None:
+            om = np.zeros(3) if omega is None else np.asarray(omega, dtype=np.float64)
+            ac = np.zeros(3) if acc is None else np.asarray(acc, dtype=np.float64)
+            imu = (om * dt, ac * dt * dt)
         x = [None] * H
         new_rho = [None] * H
         for h in range(H):
@@ -98,7 +107,7 @@ class Filter:
             st = self.state[h]
             top = h == H - 1
             names = ("w", "rho") if top else ("w", "dw", "rho", "Y")
-            pred = predict.predict(g, {k: st[k] for k in names}, self.N[h], self.readings)
+            pred = predict.predict(g, {k: st[k] for k in names}, self.N[h], self.readings, imu)
             Yhat_new, dY1, dY2 = bright[h]
             gradY = models.to_tangent(g.dmu, g.b1, g.b2, dY1, dY2)
             rhohat, dr1, dr2 = depth[h]

@@ -149,6 +149,28 @@ def _half_step(fields, geo, R, C, N, axis, rd):
     return new
 
 
+def _cross(a, b):
+    return np.array([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
+                     a[0] * b[1] - a[1] * b[0]])
+
+
+def _inertial_step(fields, geo, R, C, N, om, acc):
+    """Explicit step 1/N of the inertial source terms, pixel by pixel: w gains
+    -2 Omega x w - (Omega (Omega . eta) - eta |Omega|^2) - rho a, dw gains -2 Omega x dw."""
+    dt = 1.0 / N
+    new = {k: dict(v) for k, v in fields.items()}
+    oo = float(om @ om)
+    for i in range(R):
+        for j in range(C):
+            e = geo[i, j][0]
+            w = fields["w"][i, j]
+            cen = om * float(om @ e) - e * oo
+            new["w"][i, j] = w + dt * (-2.0 * _cross(om, w) - cen - fields["rho"][i, j] * acc)
+            if "dw" in fields:
+                new["dw"][i, j] = fields["dw"][i, j] - 2.0 * dt * _cross(om, fields["dw"][i, j])
+    return new
+
+
 def _to_dict(a):
     R, C = a.shape[:2]
     return {(i, j): (a[i, j].copy() if a.ndim == 3 else float(a[i, j]))
@@ -212,7 +234,7 @@ class LiteralFilter:
         self.state = None
         self.dt_prev = None
 
-    def push(self, Y, rho, dt):
+    def push(self, Y, rho, dt, omega=None, acc=None):
         Ys, rhos = [np.asarray(Y, float)], [np.asarray(rho, float)]
         for _ in range(1, self.H):
             Ys.append(_blur_decimate(Ys[-1]))
@@ -252,6 +274,10 @@ class LiteralFilter:
             for _ in range(N):
                 f = _half_step(f, geo, R, C, N, 1, self.rd)
                 f = _half_step(f, geo, R, C, N, 0, self.rd)
+                if omega is not None or acc is not None:
+                    om = np.zeros(3) if omega is None else np.asarray(omega, float) * dt
+                    ac = np.zeros(3) if acc is None else np.asarray(acc, float) * dt * dt
+                    f = _inertial_step(f, geo, R, C, N, om, ac)
             g1, g2, g3, g4, g5 = self.gam[h]
             x = np.zeros((R, C, 3))
             rn = np.zeros((R, C))

@@ -21,6 +21,20 @@ Top level: fields {w, rho} transported by w.  Lower levels: {w, dw, rho, Y} all
 transported by the level's reconstructed flow w, with dw and rho also carrying the
 source term with <eta, w> (w of the same level: the printed eq:invdepth_propagation_low
 has w^H in the transport term, read as w^h).
+
+Inertial source terms (optional).  The paper drops the terms -Omega x w + a_w of
+eq:hflow_conservation (eq:assumption), where a_w = -rho a - Omega x (w + Omega x eta) is the
+field acceleration of Section "Structure Flow".  (The printed a_w has +rho a; differentiating
+w = -Omega x eta - rho v with dv/dt = -Omega x v + a, eq:camvel_dot, gives -rho a, and the
+accelerating-plane pin fails with the printed sign.)  When the camera's angular velocity Omega
+and linear acceleration a are given (in the filter's time unit: rad/frame and 1/frame^2), each
+step ends with an explicit step of length dt of
+    dw/dt  = -2 Omega x w - Omega x (Omega x eta) - rho a       (w, every level)
+    ddw/dt = -2 Omega x dw                                      (dw, lower levels)
+The increment dw = w_h - up(w_{h+1}) takes the part that is linear in the field: the terms
+that do not depend on it cancel between a level and its parent up to the difference of
+their inverse depths.  rho and Y have no inertial terms (eq:invdepth_conservation,
+eq:image_conservation).
 """
 from __future__ import annotations
 
@@ -70,12 +84,29 @@ def half_step(grid, fields: dict, axis: int, N: int, readings, sourced: dict) ->
     return out
 
 
-def predict(grid, fields: dict, N: int, readings) -> dict:
+def inertial_step(grid, fields: dict, dt: float, imu) -> dict:
+    """An explicit step of length dt of the inertial source terms; imu = (Omega, a) as
+    3-vectors in rad/frame and 1/frame^2."""
+    om = np.asarray(imu[0], dtype=np.float64)
+    acc = np.asarray(imu[1], dtype=np.float64)
+    out = dict(fields)
+    w = fields["w"]
+    centripetal = np.cross(om, np.cross(om, grid.eta))
+    out["w"] = w + dt * (-2.0 * np.cross(om, w) - centripetal - fields["rho"][..., None] * acc)
+    if "dw" in fields:
+        out["dw"] = fields["dw"] + dt * (-2.0 * np.cross(om, fields["dw"]))
+    return out
+
+
+def predict(grid, fields: dict, N: int, readings, imu=None) -> dict:
     """Integrate the fields over one frame; `fields` must contain the transporting 'w'.
+    imu: None (the paper's eq:assumption) or (Omega, a) in rad/frame and 1/frame^2.
     Returns the predicted fields (the k+ state)."""
     sourced = {"w": True, "dw": True, "rho": True, "Y": False}
     f = {k: v.copy() for k, v in fields.items()}
     for _ in range(N):
         f = half_step(grid, f, 1, N, readings, sourced)
         f = half_step(grid, f, 0, N, readings, sourced)
+        if imu is not None:
+            f = inertial_step(grid, f, 1.0 / N, imu)
     return f

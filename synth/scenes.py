@@ -310,6 +310,14 @@ class Sequence:
             rho = rho_true * (1.0 + self.depth_noise * z)
         return Frame(Y=Y, rho=rho, w_gt=w, rho_true=rho_true)
 
+    def imu(self, k: int):
+        """What an inertial measurement unit on the camera reports for the interval from frame
+        k - 1 to frame k, as the filter takes it (constant over the interval): the body-frame
+        angular velocity at mid-interval (rad/s) and the inertial linear acceleration in the
+        camera frame (m/s^2; zero, since the inertial velocity is constant)."""
+        tm = 0.5 * (self.times[k - 1] + self.times[k]) if k > 0 else self.times[0]
+        return np.asarray(self.traj.omega(tm), dtype=np.float64), np.zeros(3)
+
     def pixel_flow(self, k: int = 0, device="cpu") -> "torch.Tensor":
         """Instantaneous ground-truth image motion in pixels per frame (rows, cols, 2),
         from the pinhole projection of eta_dot = P_eta w."""
