@@ -64,14 +64,23 @@ def check_bar(e, storage, what):
     assert e["mean"] <= bar and e["p99"] <= bar and e["max"] <= maxbar, (what, e)
 
 
-def compare_outputs(g, o, storage, what="", rho_outliers=0.0):
+def compare_outputs(g, o, storage, what="", rho_outliers=None):
     """Every sf_get_flow kind of the GPU filter g against the oracle o's flow() after the same
     frames: structure flow in rad/frame and rad/s (endpoint error), tangent flow (the 2-vector's
     error in pixels, eq:tangent_flow), normal flow (pixels, eq:normal_flow) and the inverse
-    depth (within the stored precision's rounding).  Returns the endpoint-error statistics of
-    the rad/frame flow."""
+    depth (within the stored precision's rounding, except a fraction rho_outliers of pixels).
+    Returns the endpoint-error statistics of the rad/frame flow.
+
+    Inverse-depth outliers: the inverse depth is transported by the flow (eq:invdepth_
+    conservation), so where the two flows differ by a fraction of a pixel at a depth
+    discontinuity of height J the transported values differ by about J times that fraction.
+    FP16 storage (flow bar 2e-2 px, inverse depth in [0, 0.5] on the scenes here) therefore
+    allows 1e-3 of the pixels to differ by up to 2e-2; FP32 allows none by default (near ties
+    of the dominant flow, eq:dominant_b1/b2, are the callers' business: up to 1e-3 there)."""
     from paper_2406_18031_amd import sflow
     dmu = o.grids[0].dmu
+    if rho_outliers is None:
+        rho_outliers = 1e-3 if storage == 1 else 0.0
 
     def kind(k):
         return g.flow(k).cpu().numpy().astype(np.float64)
@@ -94,7 +103,8 @@ def compare_outputs(g, o, storage, what="", rho_outliers=0.0):
     bad = ~np.isclose(r, want, atol=atol, rtol=rtol)
     assert bad.mean() <= rho_outliers, (what, "rho", int(bad.sum()),
                                         float(np.abs(r - want).max()))
-    np.testing.assert_allclose(r, want, atol=max(atol, 1e-3 if rho_outliers else 0.0))
+    out_max = (2e-2 if storage == 1 else 1e-3) if rho_outliers else 0.0
+    np.testing.assert_allclose(r, want, rtol=rtol, atol=max(atol, out_max))
     log(f"    {what}: w {e['mean']:.2e}/{e['p99']:.2e}/{e['max']:.2e} "
         f"tangent {et['mean']:.2e}/{et['p99']:.2e}/{et['max']:.2e} "
         f"normal {en['mean']:.2e}/{en['p99']:.2e}/{en['max']:.2e} (mean/p99/max px) "

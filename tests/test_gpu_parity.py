@@ -43,7 +43,7 @@ def _close_rho(got, want, outliers):
 
 
 def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None,
-         compare_state=True, rho_outliers=0.0):
+         compare_state=True, rho_outliers=None):
     o, g = make_pair(R, C, H, mf, smooth, cam, storage=storage, read_flags=read_flags)
     worst = 0.0
     for k, (Y, rho) in enumerate(frames):
@@ -60,7 +60,7 @@ def _run(frames, R, C, H, mf, smooth, cam, storage=0, read_flags=0, dts=None,
             assert dt_prev == dt
             for h in range(H):
                 np.testing.assert_allclose(st[h]["Y"], o.state[h]["Y"], atol=2e-6)
-                _close_rho(st[h]["rho"], o.state[h]["rho"], rho_outliers)
+                _close_rho(st[h]["rho"], o.state[h]["rho"], rho_outliers or 0.0)
     g.close()
     return worst
 
