@@ -39,7 +39,10 @@ LevelGeometry = geometry.Grid
 class Filter:
     def __init__(self, rows: int, cols: int, levels: int, max_flow_px: float, smooth_iters,
                  fx: float, fy: float, cx: float, cy: float, alpha=DEFAULT_ALPHA,
-                 readings: Readings = Readings()):
+                 readings: Readings = Readings(), eta=None):
+        """eta: None for the pinhole grid of the intrinsics, or the finest level's unit
+        directions (rows, cols, 3) of a general grid (Section "Spherical image data
+        structure"); fx then is the nominal focal length of the weights' scaling."""
         if levels < 1:
             raise ValueError("levels must be >= 1")
         self.rows, self.cols, self.levels = int(rows), int(cols), int(levels)
@@ -49,7 +52,8 @@ class Filter:
             raise ValueError("one smoothing count per level is needed")
         self.readings = readings
         self.alpha = tuple(float(a) for a in alpha)
-        self.grids = [geometry.Grid(rows, cols, fx, fy, cx, cy, h) for h in range(1, levels + 1)]
+        self.grids = [geometry.Grid(rows, cols, fx, fy, cx, cy, h, eta)
+                      for h in range(1, levels + 1)]
         for g in self.grids:
             if g.rows < 2 or g.cols < 2:
                 raise ValueError("every pyramid level needs at least 2x2 pixels")

@@ -14,7 +14,8 @@ orientation of b2 is checked against the previous row.
 
 The pinhole grid of level h samples the level-1 grid at every 2^(h-1)-th pixel,
 eta^h_{ij} = eta^1_{2^(h-1) i, 2^(h-1) j}, which is the pinhole with fx, fy, cx, cy
-divided by 2^(h-1).
+divided by 2^(h-1).  A general grid of unit directions (a Spherepix patch, an equiangular or
+fisheye camera) is given as its finest level, and the coarser levels sample it the same way.
 """
 from __future__ import annotations
 
@@ -73,14 +74,29 @@ def tangent_frame(eta: np.ndarray):
     return b1, c, dmu
 
 
-class Grid:
-    """Geometry of one pyramid level."""
+def subsample(eta1: np.ndarray, level: int) -> np.ndarray:
+    """Level h of a grid given at the finest level: every 2^(h-1)-th direction."""
+    s = 2 ** (level - 1)
+    return np.ascontiguousarray(eta1[::s, ::s])
 
-    def __init__(self, rows, cols, fx, fy, cx, cy, level):
+
+class Grid:
+    """Geometry of one pyramid level: the pinhole grid of the intrinsics, or, with eta1 (the
+    finest level's unit directions, (rows, cols, 3)), that grid sampled for the level (the
+    intrinsics then only give the nominal focal length of the weights, readings.gammas)."""
+
+    def __init__(self, rows, cols, fx, fy, cx, cy, level, eta1=None):
         self.level = level
         self.rows, self.cols = level_shape(rows, cols, level)
         self.fx, self.fy, self.cx, self.cy = level_intrinsics(fx, fy, cx, cy, level)
-        self.eta = pinhole_eta(self.rows, self.cols, self.fx, self.fy, self.cx, self.cy)
+        if eta1 is None:
+            self.eta = pinhole_eta(self.rows, self.cols, self.fx, self.fy, self.cx, self.cy)
+        else:
+            eta1 = np.asarray(eta1, dtype=np.float64)
+            if eta1.shape != (rows, cols, 3):
+                raise ValueError("eta must be (rows, cols, 3)")
+            self.eta = subsample(eta1, level)
+            assert self.eta.shape == (self.rows, self.cols, 3)
         self.P = projector(self.eta)
         self.b1, self.b2, self.dmu = tangent_frame(self.eta)
         # B as (rows, cols, 3, 2) with columns b1, b2

@@ -26,26 +26,31 @@ def _eta(i, j, fx, fy, cx, cy):
     return r / math.sqrt(r @ r)
 
 
-def _geometry(R, C, fx, fy, cx, cy):
+def _geometry(R, C, fx, fy, cx, cy, ray=None):
+    """Per-pixel (eta, P, b1, b2, dmu); ray(i, j) gives the unit direction of a general grid
+    (default: the pinhole of the intrinsics)."""
+    if ray is None:
+        def ray(i, j):
+            return _eta(i, j, fx, fy, cx, cy)
     geo = {}
     for i in range(R):
         for j in range(C):
-            e = _eta(i, j, fx, fy, cx, cy)
+            e = ray(i, j)
             P = np.eye(3) - np.outer(e, e)
             if j + 1 < C:
-                q = P @ _eta(i, j + 1, fx, fy, cx, cy)
+                q = P @ ray(i, j + 1)
                 b1 = q / np.linalg.norm(q)
             else:
-                q = P @ _eta(i, j - 1, fx, fy, cx, cy)
+                q = P @ ray(i, j - 1)
                 b1 = -q / np.linalg.norm(q)
             dmu = float(np.linalg.norm(q))
             b2 = np.cross(e, b1)
             b2 = b2 / np.linalg.norm(b2)
             if i + 1 < R:
-                if b2 @ _eta(i + 1, j, fx, fy, cx, cy) < 0:
+                if b2 @ ray(i + 1, j) < 0:
                     b2 = -b2
             elif i - 1 >= 0:
-                if b2 @ _eta(i - 1, j, fx, fy, cx, cy) > 0:
+                if b2 @ ray(i - 1, j) > 0:
                     b2 = -b2
             geo[i, j] = (e, P, b1, b2, dmu)
     return geo
@@ -217,7 +222,7 @@ class LiteralFilter:
     """Same interface as oracle.Filter (push / flow('w_frame') / state)."""
 
     def __init__(self, rows, cols, levels, max_flow_px, smooth_iters, fx, fy, cx, cy,
-                 alpha=DEFAULT_ALPHA, readings=Readings()):
+                 alpha=DEFAULT_ALPHA, readings=Readings(), eta=None):
         self.R, self.C, self.H = rows, cols, levels
         self.smooth = list(smooth_iters)
         self.rd = readings
@@ -226,7 +231,14 @@ class LiteralFilter:
         for h in range(1, levels + 1):
             s = 2.0 ** (h - 1)
             self.sizes.append((r, c))
-            self.geos.append(_geometry(r, c, fx / s, fy / s, cx / s, cy / s))
+            if eta is None:
+                self.geos.append(_geometry(r, c, fx / s, fy / s, cx / s, cy / s))
+            else:
+                step = int(s)
+
+                def ray(i, j, step=step):
+                    return np.asarray(eta[i * step, j * step], dtype=float)
+                self.geos.append(_geometry(r, c, fx / s, fy / s, cx / s, cy / s, ray))
             self.N.append(max(1, math.ceil(max_flow_px / s)))
             self.gam.append(gammas(alpha, fx / s))
             r, c = (r + 1) // 2, (c + 1) // 2

@@ -49,6 +49,30 @@ class Camera:
         return r / torch.linalg.norm(r, dim=-1, keepdim=True)
 
 
+def equiangular_rays(rows: int, cols: int, hfov_deg: float) -> np.ndarray:
+    """Unit directions (rows, cols, 3) of an equiangular (longitude-latitude) grid centred on
+    the optical axis: column j at longitude (j - (cols-1)/2) d, row i at latitude
+    (i - (rows-1)/2) d, with d = hfov / (cols - 1); eta = (sin lon cos lat, sin lat,
+    cos lon cos lat) (x right, y down, z forward).  A wide-angle grid on which pinhole pixels
+    would be far from uniform."""
+    d = np.radians(hfov_deg) / (cols - 1)
+    lon = (np.arange(cols) - (cols - 1) / 2.0) * d
+    lat = (np.arange(rows) - (rows - 1) / 2.0) * d
+    La, Lo = np.meshgrid(lat, lon, indexing="ij")
+    return np.stack([np.sin(Lo) * np.cos(La), np.sin(La), np.cos(Lo) * np.cos(La)], axis=-1)
+
+
+@dataclasses.dataclass
+class GridCamera(Camera):
+    """A camera whose pixels look along a given grid of unit directions (rows, cols, 3);
+    fx, fy, cx, cy describe a nominal pinhole of the same angular resolution (used to scale
+    motion to a target image motion)."""
+    eta: Optional[np.ndarray] = None
+
+    def rays(self, device="cpu") -> "torch.Tensor":
+        return torch.as_tensor(self.eta, dtype=torch.float64, device=device)
+
+
 def _skew(w: np.ndarray) -> np.ndarray:
     return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
 
