@@ -273,6 +273,25 @@ sf_status sf_net_train_step(sf_net net, const float* in, const float* target, fl
 /* the loss's eps (pixels, > 0; default 1e-3: close to the endpoint error itself; about 1
  * makes the loss quadratic for errors below a pixel) */
 sf_status sf_net_set_loss(sf_net net, float eps);
+/* ---- the network's forward pass without allocation ---------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the forward pass of sf_net_forward on one image,
+ * with no network object and no allocation of any kind.  Its work buffers live in a fixed
+ * array of the library's device code (about 29 MiB, held on every GPU the call runs on until
+ * the process ends), which limits the image to SF_NOALLOC_MAX_PIXELS pixels.
+ *  params  device, SF_LEARNED_PARAMS float32 values in the layout of sf_set_learned (not
+ *          checked for finiteness: non-finite parameters give non-finite outputs)
+ *  in      device, float32 [9][rows][cols] contiguous (the inputs of sf_net_forward)
+ *  out     device, float32 [3][rows][cols] contiguous
+ * The work is enqueued on hip_stream (NULL = default stream) and not waited for.  The result is
+ * bitwise that of sf_net_forward on a network holding the same parameters.  All calls on one
+ * GPU share the one array: calls that overlap in time on the same GPU (other streams, other
+ * threads) race and give undefined results; calls ordered on one stream are safe.
+ * SF_ERR_INVALID_ARG for a size outside [1, SF_NOALLOC_MAX_PIXELS] or a pointer that is not a
+ * device pointer (nothing is enqueued); the text is sf_net_last_error(NULL). */
+#define SF_NOALLOC_MAX_PIXELS (1 << 18)
+sf_status sf_net_forward_noalloc(const float* params, int32_t rows, int32_t cols,
+                                 const float* in, float* out, void* hip_stream);
 /* releases the network and its device memory (synchronises its stream); NULL is a no-op */
 sf_status sf_net_destroy(sf_net net);
 const char* sf_net_last_error(sf_net net);

@@ -4,7 +4,9 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -41,7 +43,9 @@ struct sf_net_s {
     float eps = 1e-3f;              // Charbonnier epsilon of the loss, pixels
 };
 
-static std::string g_net_create_error;
+// text of the last failure of a call without a network (sf_net_create,
+// sf_net_forward_noalloc); a fixed buffer, so that reporting an error allocates nothing
+static char g_net_create_error[512];
 
 static sf_status nfail(sf_net n, sf_status s, const char* fmt, ...) {
     char buf[512];
@@ -49,7 +53,7 @@ static sf_status nfail(sf_net n, sf_status s, const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (n) n->err = buf; else g_net_create_error = buf;
+    if (n) n->err = buf; else memcpy(g_net_create_error, buf, sizeof buf);
     return s;
 }
 
@@ -121,6 +125,52 @@ static sf_status forward(sf_net n) {
     }
     return SF_OK;
 }
+
+// ---- the forward pass without allocation (sf_net_forward_noalloc) ---------------------------
+// Its buffers live in one file-scope device array, `scratch`, laid out for one image of at
+// most SF_NOALLOC_MAX_PIXELS pixels: the packed weights (forward and input-gradient BF16
+// [4][9][16][16], the latter unused but written by the packing kernel), the biases, the input
+// planes, two ping-pong BF16 NHWC activation buffers and the output planes.  Every call
+// rewrites every byte it reads (the input planes' padding included), so nothing needs
+// clearing between calls.  Host code never passes `scratch` itself to a kernel: its name is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress, taken once per device.
+namespace {
+constexpr size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t kNaPx = SF_NOALLOC_MAX_PIXELS;    // a multiple of 16
+static_assert(kNaPx % 16 == 0, "the padded image must fit");
+constexpr size_t kNaWf = 0;
+constexpr size_t kNaWb = kNaWf + al256(4 * 9 * 256 * sizeof(uint16_t));
+constexpr size_t kNaBias = kNaWb + al256(4 * 9 * 256 * sizeof(uint16_t));
+constexpr size_t kNaIn = kNaBias + al256(4 * 16 * sizeof(float));
+constexpr size_t kNaAct0 = kNaIn + al256((size_t)kCnnInputs * kNaPx * sizeof(float));
+constexpr size_t kNaAct1 = kNaAct0 + al256(kNaPx * 16 * sizeof(uint16_t));
+constexpr size_t kNaOut = kNaAct1 + al256(kNaPx * 16 * sizeof(uint16_t));
+constexpr size_t kNaBytes = kNaOut + al256(3 * kNaPx * sizeof(float));
+constexpr int kNaMaxDevices = 64;
+
+__device__ __align__(256) char scratch[kNaBytes];
+
+std::mutex g_na_mu;
+char* g_na_ptr[kNaMaxDevices] = {};   // device address of `scratch` per device
+
+// the current device's address of `scratch` (looked up on the first call on that device)
+hipError_t noalloc_scratch(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_na_ptr[dev] = (char*)p;
+    }
+    *out = g_na_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
 
 extern "C" {
 
@@ -331,6 +381,66 @@ sf_status sf_net_train_step(sf_net n, const float* in, const float* target, floa
     return SF_OK;
 }
 
+sf_status sf_net_forward_noalloc(const float* params, int32_t rows, int32_t cols,
+                                 const float* in, float* out, void* hip_stream) {
+    if (rows < 1 || cols < 1 || (int64_t)rows * cols > (int64_t)kNaPx)
+        return nfail(nullptr, SF_ERR_INVALID_ARG,
+                     "image size must be in [1, %d] pixels (rows %d, cols %d)",
+                     (int)kNaPx, rows, cols);
+    if (!dev_ptr(params) || !dev_ptr(in) || !dev_ptr(out))
+        return nfail(nullptr, SF_ERR_INVALID_ARG, "params, in and out must be device pointers");
+    char* base = nullptr;
+    hipError_t e = noalloc_scratch(&base);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return nfail(nullptr, SF_ERR_HIP, "hipGetSymbolAddress of the scratch array failed: %s",
+                     hipGetErrorString(e));
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    CnnSegs sg{};
+    sg.n = 1;
+    sg.base[0] = 0;
+    sg.off[0] = 0;
+    sg.rows[0] = rows;
+    sg.cols[0] = cols;
+    sg.total = (int)(((int64_t)rows * cols + 15) / 16 * 16);
+    sg.base[1] = sg.total;
+    sg.off[1] = rows * cols;
+    uint16_t* act[2] = {(uint16_t*)(base + kNaAct0), (uint16_t*)(base + kNaAct1)};
+    float* planes_in = (float*)(base + kNaIn);
+    float* planes_out = (float*)(base + kNaOut);
+    PackArgs p{};
+    layer_offsets(p.woff, p.boff, p.cin, p.cout);
+    p.params = params;
+    p.wf = (uint16_t*)(base + kNaWf);
+    p.wb = (uint16_t*)(base + kNaWb);
+    p.bias = (float*)(base + kNaBias);
+    e = launch_pack_weights(p, s);
+    if (e == hipSuccess) e = launch_planes_in(sg, in, kCnnInputs, planes_in, s);
+    if (e == hipSuccess) e = launch_pack_inputs(planes_in, kCnnInputs, sg.total, act[0], s);
+    for (int l = 0; l < kCnnLayers && e == hipSuccess; ++l) {
+        // the layers of sf_net_forward's forward pass, activations ping-ponging between two
+        // buffers (inference keeps no layer inputs for a backward pass)
+        ConvArgs a{};
+        a.segs = sg;
+        a.in = act[l & 1];
+        a.w = p.wf + (size_t)l * 9 * 256;
+        a.bias = p.bias + l * 16;
+        a.relu = l < kCnnLayers - 1;
+        a.nout = l < kCnnLayers - 1 ? 16 : 3;
+        a.out = l < kCnnLayers - 1 ? act[(l + 1) & 1] : nullptr;
+        a.out_f32 = planes_out;
+        e = launch_conv(a, l == kCnnLayers - 1, s);
+    }
+    if (e == hipSuccess) e = launch_planes_out(sg, planes_out, 3, out, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return nfail(nullptr, SF_ERR_HIP, "launching the forward pass failed: %s",
+                     hipGetErrorString(e));
+    }
+    return SF_OK;
+}
+
 sf_status sf_net_set_loss(sf_net n, float eps) {
     sf_status st = net_alive(n);
     if (st != SF_OK) return st;
@@ -348,7 +458,7 @@ sf_status sf_net_destroy(sf_net n) {
 }
 
 const char* sf_net_last_error(sf_net n) {
-    return n ? n->err.c_str() : g_net_create_error.c_str();
+    return n ? n->err.c_str() : g_net_create_error;
 }
 
 }  // extern "C"

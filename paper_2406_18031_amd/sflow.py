@@ -35,6 +35,7 @@ FLOW_COMPONENTS = {SF_FLOW_W_RAD_S: 3, SF_FLOW_TANGENT_PX: 2, SF_FLOW_NORMAL_PX:
 DEFAULT_ALPHA = (300.0, 1000.0, 1.0, 1.0, 1.0)
 SF_LEARNED_PARAMS = 6387
 SF_UPDATE_INPUT_PLANES = 22
+SF_NOALLOC_MAX_PIXELS = 1 << 18
 
 
 class sf_config(ctypes.Structure):
@@ -105,6 +106,7 @@ def _load():
         "sf_net_set_loss": (st, [vp, ctypes.c_float]),
         "sf_net_destroy": (st, [vp]),
         "sf_net_last_error": (ctypes.c_char_p, [vp]),
+        "sf_net_forward_noalloc": (st, [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -122,7 +124,7 @@ EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_st
             "sf_get_state_stream", "sf_set_state_stream", "sf_set_learned", "sf_learned_stats",
             "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
             "sf_net_forward", "sf_net_train_step", "sf_net_set_loss", "sf_net_destroy",
-            "sf_net_last_error")
+            "sf_net_last_error", "sf_net_forward_noalloc")
 
 
 def _check(status: int, ctx) -> None:
@@ -317,6 +319,11 @@ def _net_check(status: int, net) -> None:
         raise SflowError(status, msg.decode() if msg else "")
 
 
+def sf_net_last_error(net: Optional[int]) -> str:
+    msg = lib.sf_net_last_error(net)
+    return msg.decode() if msg else ""
+
+
 def sf_net_create(sizes: Sequence[Sequence[int]], stream=None) -> int:
     n = len(sizes)
     rows = (ctypes.c_int32 * max(n, 1))(*[int(r) for r, _ in sizes])
@@ -339,6 +346,13 @@ def sf_net_get_params(net: int) -> np.ndarray:
 
 def sf_net_forward(net: int, inp, out) -> None:
     _net_check(lib.sf_net_forward(net, _ptr(inp), _ptr(out)), net)
+
+
+def sf_net_forward_noalloc(params, rows: int, cols: int, inp, out, stream=None) -> None:
+    """params, inp, out: device tensors (float32; SF_LEARNED_PARAMS, [9][rows][cols],
+    [3][rows][cols])."""
+    _net_check(lib.sf_net_forward_noalloc(_ptr(params), rows, cols, _ptr(inp), _ptr(out),
+                                          _stream(stream)), None)
 
 
 def sf_net_train_step(net: int, inp, target, lr: float, want_grad: bool = False):
