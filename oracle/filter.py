@@ -17,10 +17,11 @@ push(Y, rho, dt) for frame k+1:
   S7  inverse-depth update                                   (update.py)
   S8  reconstruction w_h = up(w_{h+1}) + dw_h, h = H-1..1     (pyramid.py)
   S9  Yhat_h <- brightness model of the new frame
-With the camera's angular velocity Omega (rad/s) and linear acceleration a (m/s^2), both in
-the camera frame and taken as constant between the two frames (Section "Structure Flow"),
-push(..., omega, acc) keeps the inertial source terms that the paper drops by eq:assumption
-(predict.py): Omega dt and a dt^2 in the filter's time unit.
+With the camera's angular velocity Omega (rad/s), angular acceleration dOmega (rad/s^2) and
+linear acceleration a (m/s^2), all in the camera frame and taken as constant between the two
+frames (Section "Structure Flow"), push(..., omega, omega_dot, acc) keeps the inertial source
+terms that the paper drops by eq:assumption (predict.py): Omega dt, dOmega dt^2 and a dt^2 in
+the filter's time unit.
 The first frame only initialises: w = dw = 0, rho = measured rho (0 where missing),
 Yhat from the frame.  dt (seconds) only converts the output to rad/s: the scheme runs in
 frames.  When dt changes between frames, w and dw are rescaled by dt_new/dt_old so that
@@ -70,7 +71,7 @@ class Filter:
             rhos.append(pyramid.downsample_valid(rhos[-1]))
         return Ys, rhos
 
-    def push(self, Y, rho, dt: float, omega=None, acc=None):
+    def push(self, Y, rho, dt: float, omega=None, acc=None, omega_dot=None):
         Y = np.asarray(Y, dtype=np.float64)
         rho = np.asarray(rho, dtype=np.float64)
         if Y.shape != (self.rows, self.cols) or rho.shape != (self.rows, self.cols):
@@ -100,10 +101,10 @@ class Filter:
                 if "dw" in st:
                     st["dw"] = st["dw"] * c
         imu = None
-        if omega is not None or acc is not None:
-            om = np.zeros(3) if omega is None else np.asarray(omega, dtype=np.float64)
-            ac = np.zeros(3) if acc is None else np.asarray(acc, dtype=np.float64)
-            imu = (om * dt, ac * dt * dt)
+        if omega is not None or acc is not None or omega_dot is not None:
+            def vec(v):
+                return np.zeros(3) if v is None else np.asarray(v, dtype=np.float64)
+            imu = (vec(omega) * dt, vec(omega_dot) * dt * dt, vec(acc) * dt * dt)
         x = [None] * H
         new_rho = [None] * H
         for h in range(H):

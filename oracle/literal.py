@@ -159,9 +159,10 @@ def _cross(a, b):
                      a[0] * b[1] - a[1] * b[0]])
 
 
-def _inertial_step(fields, geo, R, C, N, om, acc):
+def _inertial_step(fields, geo, R, C, N, om, dom, acc):
     """Explicit step 1/N of the inertial source terms, pixel by pixel: w gains
-    -2 Omega x w - (Omega (Omega . eta) - eta |Omega|^2) - rho a, dw gains -2 Omega x dw."""
+    -2 Omega x w - (Omega (Omega . eta) - eta |Omega|^2) - dOmega x eta - rho a, dw gains
+    -2 Omega x dw."""
     dt = 1.0 / N
     new = {k: dict(v) for k, v in fields.items()}
     oo = float(om @ om)
@@ -170,7 +171,8 @@ def _inertial_step(fields, geo, R, C, N, om, acc):
             e = geo[i, j][0]
             w = fields["w"][i, j]
             cen = om * float(om @ e) - e * oo
-            new["w"][i, j] = w + dt * (-2.0 * _cross(om, w) - cen - fields["rho"][i, j] * acc)
+            new["w"][i, j] = w + dt * (-2.0 * _cross(om, w) - cen - _cross(dom, e)
+                                       - fields["rho"][i, j] * acc)
             if "dw" in fields:
                 new["dw"][i, j] = fields["dw"][i, j] - 2.0 * dt * _cross(om, fields["dw"][i, j])
     return new
@@ -246,7 +248,7 @@ class LiteralFilter:
         self.state = None
         self.dt_prev = None
 
-    def push(self, Y, rho, dt, omega=None, acc=None):
+    def push(self, Y, rho, dt, omega=None, acc=None, omega_dot=None):
         Ys, rhos = [np.asarray(Y, float)], [np.asarray(rho, float)]
         for _ in range(1, self.H):
             Ys.append(_blur_decimate(Ys[-1]))
@@ -286,10 +288,11 @@ class LiteralFilter:
             for _ in range(N):
                 f = _half_step(f, geo, R, C, N, 1, self.rd)
                 f = _half_step(f, geo, R, C, N, 0, self.rd)
-                if omega is not None or acc is not None:
+                if omega is not None or acc is not None or omega_dot is not None:
                     om = np.zeros(3) if omega is None else np.asarray(omega, float) * dt
+                    do = np.zeros(3) if omega_dot is None else np.asarray(omega_dot, float) * dt * dt
                     ac = np.zeros(3) if acc is None else np.asarray(acc, float) * dt * dt
-                    f = _inertial_step(f, geo, R, C, N, om, ac)
+                    f = _inertial_step(f, geo, R, C, N, om, do, ac)
             g1, g2, g3, g4, g5 = self.gam[h]
             x = np.zeros((R, C, 3))
             rn = np.zeros((R, C))

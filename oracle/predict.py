@@ -26,11 +26,13 @@ Inertial source terms (optional).  The paper drops the terms -Omega x w + a_w of
 eq:hflow_conservation (eq:assumption), where a_w = -rho a - Omega x (w + Omega x eta) is the
 field acceleration of Section "Structure Flow".  (The printed a_w has +rho a; differentiating
 w = -Omega x eta - rho v with dv/dt = -Omega x v + a, eq:camvel_dot, gives -rho a, and the
-accelerating-plane pin fails with the printed sign.)  When the camera's angular velocity Omega
-and linear acceleration a are given (in the filter's time unit: rad/frame and 1/frame^2), each
-step ends with an explicit step of length dt of
-    dw/dt  = -2 Omega x w - Omega x (Omega x eta) - rho a       (w, every level)
-    ddw/dt = -2 Omega x dw                                      (dw, lower levels)
+accelerating-plane pin fails with the printed sign.)  The derivation takes Omega constant
+(eq:totaldev_camangvel); when it changes, differentiating -Omega x eta adds -dOmega/dt x eta,
+which is kept too when the angular acceleration is given.  With the camera's angular velocity
+Omega, angular acceleration dOmega and linear acceleration a (in the filter's time unit:
+rad/frame, rad/frame^2, 1/frame^2), each step ends with an explicit step of length dt of
+    dw/dt  = -2 Omega x w - Omega x (Omega x eta) - dOmega x eta - rho a   (w, every level)
+    ddw/dt = -2 Omega x dw                                               (dw, lower levels)
 The increment dw = w_h - up(w_{h+1}) takes the part that is linear in the field: the terms
 that do not depend on it cancel between a level and its parent up to the difference of
 their inverse depths.  rho and Y have no inertial terms (eq:invdepth_conservation,
@@ -85,14 +87,16 @@ def half_step(grid, fields: dict, axis: int, N: int, readings, sourced: dict) ->
 
 
 def inertial_step(grid, fields: dict, dt: float, imu) -> dict:
-    """An explicit step of length dt of the inertial source terms; imu = (Omega, a) as
-    3-vectors in rad/frame and 1/frame^2."""
+    """An explicit step of length dt of the inertial source terms; imu = (Omega, dOmega, a) as
+    3-vectors in rad/frame, rad/frame^2 and 1/frame^2."""
     om = np.asarray(imu[0], dtype=np.float64)
-    acc = np.asarray(imu[1], dtype=np.float64)
+    dom = np.asarray(imu[1], dtype=np.float64)
+    acc = np.asarray(imu[2], dtype=np.float64)
     out = dict(fields)
     w = fields["w"]
     centripetal = np.cross(om, np.cross(om, grid.eta))
-    out["w"] = w + dt * (-2.0 * np.cross(om, w) - centripetal - fields["rho"][..., None] * acc)
+    out["w"] = w + dt * (-2.0 * np.cross(om, w) - centripetal - np.cross(dom, grid.eta)
+                         - fields["rho"][..., None] * acc)
     if "dw" in fields:
         out["dw"] = fields["dw"] + dt * (-2.0 * np.cross(om, fields["dw"]))
     return out
@@ -100,7 +104,8 @@ def inertial_step(grid, fields: dict, dt: float, imu) -> dict:
 
 def predict(grid, fields: dict, N: int, readings, imu=None) -> dict:
     """Integrate the fields over one frame; `fields` must contain the transporting 'w'.
-    imu: None (the paper's eq:assumption) or (Omega, a) in rad/frame and 1/frame^2.
+    imu: None (the paper's eq:assumption) or (Omega, dOmega, a) in rad/frame, rad/frame^2 and
+    1/frame^2.
     Returns the predicted fields (the k+ state)."""
     sourced = {"w": True, "dw": True, "rho": True, "Y": False}
     f = {k: v.copy() for k, v in fields.items()}

@@ -100,6 +100,11 @@ class Trajectory:
     def omega(self, t: float) -> np.ndarray:
         return self.omega0 + self.amp * np.sin(2 * np.pi * self.freq * t + self.phase)
 
+    def omega_dot(self, t: float) -> np.ndarray:
+        """d Omega / dt (body frame, rad/s^2)."""
+        w = 2 * np.pi * self.freq
+        return self.amp * w * np.cos(w * t + self.phase)
+
     def poses(self, times: np.ndarray):
         """Camera-to-world rotations R_k and positions p_k at the given increasing times
         (the first time is the reference where R = I)."""
@@ -337,10 +342,12 @@ class Sequence:
     def imu(self, k: int):
         """What an inertial measurement unit on the camera reports for the interval from frame
         k - 1 to frame k, as the filter takes it (constant over the interval): the body-frame
-        angular velocity at mid-interval (rad/s) and the inertial linear acceleration in the
-        camera frame (m/s^2; zero, since the inertial velocity is constant)."""
+        angular velocity (rad/s) and its rate of change (rad/s^2) at mid-interval, and the
+        inertial linear acceleration in the camera frame (m/s^2; zero, since the inertial
+        velocity is constant).  Returns (omega, omega_dot, acc)."""
         tm = 0.5 * (self.times[k - 1] + self.times[k]) if k > 0 else self.times[0]
-        return np.asarray(self.traj.omega(tm), dtype=np.float64), np.zeros(3)
+        return (np.asarray(self.traj.omega(tm), dtype=np.float64),
+                np.asarray(self.traj.omega_dot(tm), dtype=np.float64), np.zeros(3))
 
     def pixel_flow(self, k: int = 0, device="cpu") -> "torch.Tensor":
         """Instantaneous ground-truth image motion in pixels per frame (rows, cols, 2),

@@ -74,7 +74,7 @@ def test_texture_transport_under_rotation_on_an_equiangular_grid(om):
     change = np.abs(Y1 - Y0)[inner].max()
 
     def err(grid):
-        out = predict.predict(grid, fields, 4, Readings(), (om, np.zeros(3)))
+        out = predict.predict(grid, fields, 4, Readings(), (om, np.zeros(3), np.zeros(3)))
         return np.abs(out["Y"] - Y1)[inner].max() / change
 
     c = (R - 1) / 2

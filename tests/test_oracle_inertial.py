@@ -64,7 +64,8 @@ def test_pure_rotation_inside_a_sphere_is_stationary():
     inner = (slice(4, -4), slice(4, -4))
     drift = np.abs(np.cross(om, np.cross(om, g.eta)))[inner].max()
     for N in (2, 4, 8):
-        kept = predict.predict(g, {"w": w0, "rho": rho}, N, Readings(), (om, np.zeros(3)))
+        kept = predict.predict(g, {"w": w0, "rho": rho}, N, Readings(),
+                               (om, np.zeros(3), np.zeros(3)))
         plain = predict.predict(g, {"w": w0, "rho": rho}, N, Readings())
         assert np.abs(kept["w"] - w0)[inner].max() < 0.1 * drift
         moved = (plain["w"] - w0)[inner]
@@ -91,7 +92,7 @@ def test_plane_under_rotation_and_acceleration(case):
     w0, r0 = _plane_fields(g, n0, 2.0, V, A, om, 0.0)
     w1, r1 = _plane_fields(g, n0, 2.0, V, A, om, 1.0)
     # the acceleration in the camera frame at mid-interval (it turns with the camera)
-    imu = (om, _rotation(0.5 * om).T @ A)
+    imu = (om, np.zeros(3), _rotation(0.5 * om).T @ A)
     inner = (slice(4, -4), slice(4, -4))
     change = np.abs(w1 - w0)[inner].max()
     for N in (2, 4, 8):
@@ -99,9 +100,47 @@ def test_plane_under_rotation_and_acceleration(case):
         plain = predict.predict(g, {"w": w0, "rho": r0}, N, Readings())
         assert np.abs(kept["w"] - w1)[inner].max() < bound * change
         assert np.abs(plain["w"] - w1)[inner].max() > 0.9 * change
-        flipped = predict.predict(g, {"w": w0, "rho": r0}, N, Readings(), (om, -imu[1]))
+        flipped = predict.predict(g, {"w": w0, "rho": r0}, N, Readings(), (om, imu[1], -imu[2]))
         if case == "accelerating":
             assert np.abs(flipped["w"] - w1)[inner].max() > 1.5 * change
+
+
+def test_angular_acceleration_about_a_fixed_axis():
+    """A camera whose angular velocity grows along a fixed axis, Omega(t) = (w0 + al t) n, so
+    that its attitude is exp((w0 t + al t^2 / 2) [n]x) exactly, in front of a plane while it
+    translates.  The structure flow -Omega(t) x eta - rho v changes with Omega itself: with the
+    angular acceleration the prediction lands near the exact fields one frame later, with
+    Omega alone (the paper's constant-rate kinematics, eq:totaldev_camangvel) it misses by the
+    -dOmega x eta of the frame."""
+    n0 = np.array([0.1, -0.3, 1.0])
+    n0 /= np.linalg.norm(n0)
+    V = np.array([0.004, 0.002, 0.03])
+    axis = np.array([0.3, 1.0, -0.2])
+    axis /= np.linalg.norm(axis)
+    w0, al = 0.01, 0.006                      # rad/frame, rad/frame^2
+    R = 48
+    g = _grid(R)
+
+    def fields(t):
+        Rt = _rotation(axis * (w0 * t + 0.5 * al * t * t))
+        n = Rt.T @ n0
+        rho = (g.eta @ n) / (2.0 - n0 @ (V * t))
+        om = axis * (w0 + al * t)
+        return -np.cross(om, g.eta) - rho[..., None] * (Rt.T @ V), rho
+
+    wa, ra = fields(0.0)
+    wb, _ = fields(1.0)
+    om_mid = axis * (w0 + 0.5 * al)
+    inner = (slice(4, -4), slice(4, -4))
+    change = np.abs(wb - wa)[inner].max()
+    with_dom = predict.predict(g, {"w": wa, "rho": ra}, 8, Readings(),
+                               (om_mid, axis * al, np.zeros(3)))
+    without = predict.predict(g, {"w": wa, "rho": ra}, 8, Readings(),
+                              (om_mid, np.zeros(3), np.zeros(3)))
+    e_with = np.abs(with_dom["w"] - wb)[inner].max()
+    e_without = np.abs(without["w"] - wb)[inner].max()
+    assert e_with < 0.15 * change
+    assert e_without > 3.0 * e_with
 
 
 def test_zero_rates_give_the_plain_prediction():
@@ -110,7 +149,7 @@ def test_zero_rates_give_the_plain_prediction():
     fields = {"w": 1e-3 * rng.standard_normal((16, 16, 3)),
               "dw": 1e-4 * rng.standard_normal((16, 16, 3)),
               "rho": 0.2 + rng.random((16, 16)), "Y": rng.random((16, 16))}
-    a = predict.predict(g, fields, 3, Readings(), (np.zeros(3), np.zeros(3)))
+    a = predict.predict(g, fields, 3, Readings(), (np.zeros(3), np.zeros(3), np.zeros(3)))
     b = predict.predict(g, fields, 3, Readings())
     for k in fields:
         np.testing.assert_array_equal(a[k], b[k])
@@ -125,13 +164,14 @@ def test_vectorised_equals_per_pixel_literal_with_inertial_terms(R, C, H, mf, sm
     a = Filter(R, C, H, mf, sm, *cam)
     b = LiteralFilter(R, C, H, mf, sm, *cam)
     om = np.array([3.0, -2.0, 5.0])           # rad/s, with dt = 0.01: 0.03-0.05 rad/frame
+    dom = np.array([-20.0, 35.0, 10.0])       # rad/s^2
     acc = np.array([40.0, 10.0, -30.0])       # m/s^2
     for k in range(4):
         Y = rng.random((R, C))
         rho = 0.2 + rng.random((R, C))
         rho[rng.random((R, C)) < 0.1] = np.nan
-        a.push(Y, rho, 0.01, omega=om, acc=acc)
-        b.push(Y, rho, 0.01, omega=om, acc=acc)
+        a.push(Y, rho, 0.01, omega=om, acc=acc, omega_dot=dom)
+        b.push(Y, rho, 0.01, omega=om, acc=acc, omega_dot=dom)
         np.testing.assert_allclose(a.flow("w_frame"), b.flow("w_frame"), atol=1e-12)
         for h in range(H):
             np.testing.assert_allclose(a.state[h]["rho"], b.state[h]["rho"], atol=1e-12)
@@ -139,8 +179,9 @@ def test_vectorised_equals_per_pixel_literal_with_inertial_terms(R, C, H, mf, sm
 
 def test_inertial_terms_lower_the_error_under_rotation():
     """A box scene whose image motion is mostly from camera rotation (80 %): the filter with
-    the inertial terms (the renderer's angular velocity at mid-interval; the inertial velocity
-    is constant, so the acceleration is zero) ends closer to the true flow."""
+    the inertial terms (the renderer's angular velocity and its rate of change at
+    mid-interval; the inertial velocity is constant, so the acceleration is zero) ends closer
+    to the true flow."""
     from synth.scenes import box_sequence, render_sequence
     seq = box_sequence(96, 96, 16, seed=5, max_flow_px=4.0, rot_share=0.8)
     Y, rho, W = render_sequence(seq)
@@ -151,8 +192,8 @@ def test_inertial_terms_lower_the_error_under_rotation():
         e = []
         for k in range(seq.n_frames):
             if use and k > 0:
-                om, acc = seq.imu(k)
-                f.push(Y[k], rho[k], seq.dt, omega=om, acc=acc)
+                om, dom, acc = seq.imu(k)
+                f.push(Y[k], rho[k], seq.dt, omega=om, omega_dot=dom, acc=acc)
             else:
                 f.push(Y[k], rho[k], seq.dt)
             if k >= 6:
