@@ -115,6 +115,16 @@ typedef struct {
 
 typedef struct {
     double fx, fy, cx, cy; /* pinhole intrinsics of the finest level, in pixels; fx, fy > 0   */
+    /* Optional general grid (Section "Spherical image data structure"): NULL for the pinhole
+     * grid of the intrinsics, or a HOST array of rows x cols x 3 doubles, the finest level's
+     * unit directions (row-major, x right, y down, z forward; |eta| within 1e-6 of 1), e.g. a
+     * Spherepix patch or a wide-angle camera's rays.  Level h then samples it at every
+     * 2^(h-1)-th row and column; the tangent bases and spacings are derived from it as the
+     * paper defines them (b1 toward the next column, b2 = eta x b1 toward the next row,
+     * dmu = |P eta_next|) and kept in device tables (36 bytes per pixel per level, read by
+     * every frame).  fx still sets the weights' scaling (dmu0 in sf_config.alpha) and the FP16
+     * flow scale; cx, cy are not used.  Read during the call only. */
+    const double* eta;
 } sf_camera;
 
 /* Create a filter context.  Allocates all device memory for the state (double-buffered),
@@ -137,6 +147,23 @@ sf_status sf_set_camera(sf_ctx ctx, const sf_camera* cam);
  * change, update-input read), always on the context's stream and before that call's own work,
  * so the deferral is invisible to the caller. */
 sf_status sf_push_frame(sf_ctx ctx, const void* Y, const void* rho, double dt);
+
+/* sf_push_frame with the camera's inertial rates, host arrays of 3 doubles in the camera frame
+ * (x right, y down, z forward), each taken as constant since the previous frame and each NULL
+ * for zeros: omega, its angular velocity (rad/s); omega_dot, the rate of change of omega
+ * (rad/s^2); acc, its linear acceleration relative to an inertial frame (m/s^2)
+ * (Section "Structure Flow", eq:camvel_dot).  The prediction then keeps the source terms of
+ * eq:hflow_conservation that the paper drops by eq:assumption (Section "State prediction"):
+ * after each step of length 1/N (frames) the structure flow gains
+ * 1/N (-2 W x w - W x (W x eta) - D x eta - rho A), with W = omega dt, D = omega_dot dt^2 and
+ * A = acc dt^2, and the increment of a lower level gains 1/N (-2 W x dw).  The acceleration
+ * enters with -rho A as the kinematics give it (w = -Omega x eta - rho v for a static scene,
+ * dv/dt = -Omega x v + a; the printed field acceleration has +rho a), and -D x eta is the
+ * derivative of -Omega x eta when omega changes (the paper takes it constant,
+ * eq:totaldev_camangvel).  With all three NULL this is sf_push_frame, bitwise.
+ * SF_ERR_INVALID_ARG for a non-finite rate. */
+sf_status sf_push_frame_ex(sf_ctx ctx, const void* Y, const void* rho, double dt,
+                           const double* omega, const double* omega_dot, const double* acc);
 
 /* Write the finest-level result of the last push to out (device, float32, see SF_FLOW_*).
  * SF_ERR_STATE before the first push; zeros after only the first push. */
@@ -178,6 +205,11 @@ sf_status sf_set_cameras(sf_ctx ctx, const sf_camera* cams);
 /* Y, rho: host arrays of n device pointers (one frame per stream); dt: host array of n */
 sf_status sf_push_frames(sf_ctx ctx, const void* const* Y, const void* const* rho,
                          const double* dt);
+/* sf_push_frames with inertial rates (see sf_push_frame_ex): omega, omega_dot, acc are host
+ * arrays of 3 n doubles (stream s at [3 s, 3 s + 3)), each NULL for zeros */
+sf_status sf_push_frames_ex(sf_ctx ctx, const void* const* Y, const void* const* rho,
+                            const double* dt, const double* omega, const double* omega_dot,
+                            const double* acc);
 sf_status sf_get_flow_stream(sf_ctx ctx, int32_t stream, int32_t kind, void* out);
 /* Every stream's output in one call: outs is a host array of n device pointers (NULL = skip
  * that stream), each as out of sf_get_flow for that stream.  The results are bitwise those of
@@ -211,6 +243,17 @@ sf_status sf_set_pass_steps(sf_ctx ctx, int32_t steps);
  * last reset (synchronises the stream). */
 sf_status sf_set_timing(sf_ctx ctx, int32_t enable);
 sf_status sf_kernel_times(sf_ctx ctx, double* ms3, int64_t* launches3, int32_t reset);
+
+/* Frame graphs.  When enabled, every push after a stream's first frame replays a HIP graph
+ * instead of enqueuing its launches one by one: the frame's launches (pyramid, level steps,
+ * learned update, reconstruction) are captured once per state parity and per form of the
+ * prediction (with or without inertial rates) on a private stream, and each push updates the
+ * per-frame arguments of the pyramid and level-step nodes (input pointers, dt rescale, rates)
+ * and launches the graph on the context stream.  Results are bitwise those of the launches
+ * enqueued one by one.  Graphs are captured again after any change of cameras, tiles, pass
+ * length or learned parameters.  Not used while kernel timing is on.  Disabling releases them
+ * (synchronises the stream). */
+sf_status sf_set_graph(sf_ctx ctx, int32_t enable);
 
 /* ---- learned update ----------------------------------------------------------------------
  * An extension beyond the paper, which uses the least-squares update of Section "State
@@ -295,6 +338,14 @@ sf_status sf_net_forward_noalloc(const float* params, int32_t rows, int32_t cols
 /* releases the network and its device memory (synchronises its stream); NULL is a no-op */
 sf_status sf_net_destroy(sf_net net);
 const char* sf_net_last_error(sf_net net);
+
+/* ---- measurement -------------------------------------------------------------------------
+ * A plain streaming copy of `bytes` bytes from src to dst (device pointers, 16-byte aligned,
+ * not overlapping) on hip_stream, enqueued and not waited for: the yardstick for the HBM
+ * bandwidth the device reaches (bytes read + bytes written over its duration), and a copy of
+ * known size for scaling HBM byte counters.  SF_ERR_INVALID_ARG for host, misaligned or
+ * overlapping pointers. */
+sf_status sf_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -64,6 +64,8 @@ struct sf_ctx_s {
     LevelDev* sv_dev = nullptr;
     size_t sv_cap = 0;              // entries sv_dev can hold
     float* mid = nullptr;           // FP32 fields between passes (two sets per split level)
+    float* geo = nullptr;           // geometry tables of every level (general grids), or NULL
+    bool grid = false;              // the level steps read geometry tables
     size_t mid_bytes = 0;
     size_t lds_bytes = 0;
     int max_levels = 0;
@@ -88,6 +90,24 @@ struct sf_ctx_s {
     float* params_dev = nullptr;         // FP32 master weights
     unsigned long long* fallbacks = nullptr;
     int64_t learned_pixels = 0;
+    // Frame graphs (sf_set_graph): a frame's launches after the first frame, captured once per
+    // state parity and per form of the prediction (plain / inertial), replayed with the
+    // per-frame arguments of the pyramid and level-step nodes updated in place.
+    struct FrameArgsNode {
+        hipGraphNode_t node = nullptr;
+        hipKernelNodeParams p{};     // launch shape and kernel of the node
+        int kind = 0;                // frame_input_kind of its kernel
+        ElemArgs e{};                // its arguments (kind 1)
+        StepArgs st{};               // its arguments (kind 2)
+    };
+    struct FrameGraph {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        std::vector<FrameArgsNode> nodes;
+    };
+    bool graph_on = false;
+    hipStream_t cap = nullptr;            // private stream the frame is captured on
+    FrameGraph graphs[2][2];              // [parity][inertial]
 };
 
 static std::string g_create_error;
@@ -364,6 +384,7 @@ static int recon_tile(sf_ctx c, int level) { return big_tile(c, level, 1); }
 extern "C" {
 
 static sf_status flush_recon(sf_ctx c);
+static void drop_graphs(sf_ctx c);
 
 sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf_ctx* out) {
     if (!out) return fail(nullptr, SF_ERR_INVALID_ARG, "NULL output pointer");
@@ -563,6 +584,7 @@ static sf_status upload_levels(sf_ctx c) {
         }
         layout_blocks(c, c->mid, nl);   // with the new addresses
     }
+    drop_graphs(c);   // captured with the old layout
     c->lv = std::move(nl.lv);
     c->sv = std::move(nl.sv);
     c->step_launches = std::move(nl.launches);
@@ -576,17 +598,137 @@ static sf_status upload_levels(sf_ctx c) {
     return SF_OK;
 }
 
+// Geometry table of one level of a general grid (Section "Spherical image data structure"):
+// level h samples the finest grid eta1 (rows1 x cols1 x 3) at every 2^h-th direction; per
+// pixel b1 = P eta_next / |P eta_next| toward the next column (the previous one, negated, in
+// the last column), dmu = |P eta_next|, b2 = eta x b1 / |eta x b1| oriented toward the next row
+// (away from the previous one in the last row), stored as 9 FP32 planes of rows x gpitch:
+// b1/dmu, b2/dmu, eta.  False if two neighbouring directions coincide.
+static bool grid_table(const double* eta1, int cols1, int h, int R, int C, int gpitch,
+                       std::vector<float>& out) {
+    const int sc = 1 << h;
+    auto E = [&](int i, int j, double* e) {
+        const double* p = eta1 + ((size_t)i * sc * cols1 + (size_t)j * sc) * 3;
+        e[0] = p[0];
+        e[1] = p[1];
+        e[2] = p[2];
+    };
+    const size_t plane = (size_t)R * gpitch;
+    out.assign(9 * plane, 0.0f);
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < C; ++j) {
+            double e[3], n[3], q[3], b1[3], b2[3];
+            E(i, j, e);
+            const bool last_c = j + 1 >= C;
+            E(i, last_c ? j - 1 : j + 1, n);
+            const double en = e[0] * n[0] + e[1] * n[1] + e[2] * n[2];
+            for (int k = 0; k < 3; ++k) q[k] = n[k] - e[k] * en;
+            const double dmu = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+            if (!(dmu > 1e-12)) return false;
+            for (int k = 0; k < 3; ++k) b1[k] = (last_c ? -q[k] : q[k]) / dmu;
+            b2[0] = e[1] * b1[2] - e[2] * b1[1];
+            b2[1] = e[2] * b1[0] - e[0] * b1[2];
+            b2[2] = e[0] * b1[1] - e[1] * b1[0];
+            const double nb = sqrt(b2[0] * b2[0] + b2[1] * b2[1] + b2[2] * b2[2]);
+            if (!(nb > 1e-12)) return false;
+            for (int k = 0; k < 3; ++k) b2[k] /= nb;
+            if (R >= 2) {
+                const bool last_r = i + 1 >= R;
+                double m[3];
+                E(last_r ? i - 1 : i + 1, j, m);
+                double sgn = b2[0] * m[0] + b2[1] * m[1] + b2[2] * m[2];
+                if (last_r) sgn = -sgn;
+                if (sgn < 0)
+                    for (int k = 0; k < 3; ++k) b2[k] = -b2[k];
+            }
+            const size_t o = (size_t)i * gpitch + j;
+            for (int k = 0; k < 3; ++k) {
+                out[k * plane + o] = (float)(b1[k] / dmu);
+                out[(3 + k) * plane + o] = (float)(b2[k] / dmu);
+                out[(6 + k) * plane + o] = (float)e[k];
+            }
+        }
+    return true;
+}
+
+static int grid_pitch(int cols) { return (cols + 63) / 64 * 64; }
+
+// Pinhole rays of a finest level (the closed form of the kernels), for a stream of a batch
+// that has no grid of its own when another stream has one.
+static void pinhole_rays(const sf_camera* cam, int R, int C, std::vector<double>& eta) {
+    eta.resize((size_t)R * C * 3);
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < C; ++j) {
+            const double x = (j - cam->cx) / cam->fx, y = (i - cam->cy) / cam->fy;
+            const double n = sqrt(x * x + y * y + 1.0);
+            double* p = &eta[((size_t)i * C + j) * 3];
+            p[0] = x / n;
+            p[1] = y / n;
+            p[2] = 1.0 / n;
+        }
+}
+
 sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
     if (!cams) return fail(c, SF_ERR_INVALID_ARG, "NULL camera");
+    bool any_grid = false;
     for (int s = 0; s < c->S; ++s) {
         const sf_camera* cam = &cams[s];
         if (!(cam->fx > 0) || !(cam->fy > 0) || !isfinite(cam->fx) || !isfinite(cam->fy) ||
             !isfinite(cam->cx) || !isfinite(cam->cy))
             return fail(c, SF_ERR_INVALID_ARG,
                         "camera %d: fx, fy must be finite and > 0, cx, cy finite", s);
+        if (cam->eta) {
+            any_grid = true;
+            const size_t n = (size_t)c->st[s].cfg.rows * c->st[s].cfg.cols;
+            for (size_t p = 0; p < n; ++p) {
+                const double* e = cam->eta + 3 * p;
+                const double nn = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+                if (!isfinite(nn) || fabs(nn - 1.0) > 1e-6)
+                    return fail(c, SF_ERR_INVALID_ARG,
+                                "camera %d: eta must hold finite unit vectors (pixel %zu)", s, p);
+            }
+        }
     }
+    // geometry tables of every level of every stream (pinhole streams from their rays) when
+    // some stream has a grid; built on the host, allocated before anything is released
+    float* new_geo = nullptr;
+    std::vector<size_t> geo_off(c->lv.size(), 0);
+    if (any_grid) {
+        std::vector<float> all, tab;
+        std::vector<double> rays;
+        for (int s = 0; s < c->S; ++s) {
+            const StreamInfo& si = c->st[s];
+            const double* eta1 = cams[s].eta;
+            if (!eta1) {
+                pinhole_rays(&cams[s], si.cfg.rows, si.cfg.cols, rays);
+                eta1 = rays.data();
+            }
+            for (int h = 0; h < si.H; ++h) {
+                const LevelDev& L = c->lv[si.e0 + h];
+                if (!grid_table(eta1, si.cfg.cols, h, L.rows, L.cols, grid_pitch(L.cols), tab))
+                    return fail(c, SF_ERR_INVALID_ARG,
+                                "camera %d: neighbouring directions of level %d coincide", s,
+                                h + 1);
+                geo_off[si.e0 + h] = all.size();
+                all.insert(all.end(), tab.begin(), tab.end());
+            }
+        }
+        hipError_t e = dev_malloc((void**)&new_geo, all.size() * sizeof(float));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, e == hipErrorOutOfMemory ? SF_ERR_OOM : SF_ERR_HIP,
+                        "hipMalloc of the geometry tables failed");
+        }
+        e = hipMemcpy(new_geo, all.data(), all.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(new_geo);
+            return hip_fail(c, e, "uploading the geometry tables");
+        }
+    }
+    float* old_geo = c->geo;
+    const bool old_grid = c->grid;
     const std::vector<LevelDev> old_lv = c->lv;
     const std::vector<StreamInfo> old_st = c->st;
     for (int s = 0; s < c->S; ++s) {
@@ -615,18 +757,26 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
             L.g4 = cf.alpha[3];
             L.g5 = cf.alpha[4];
             L.qscale = (float)(1.0 / dmu0);   // half storage keeps flow in pixels per frame
+            L.geo = new_geo ? new_geo + geo_off[si.e0 + h] : nullptr;
+            L.gpitch = grid_pitch(L.cols);
         }
         si.dt_prev = 0.0;
         si.update_ran = false;
     }
+    c->grid = new_geo != nullptr;
+    c->geo = new_geo;
     sf_status s2 = upload_levels(c);
     if (s2 != SF_OK) {
         if (!c->hip_failed) {   // nothing was uploaded: the context stays as it was
             c->lv = old_lv;
             c->st = old_st;
+            c->geo = old_geo;
+            c->grid = old_grid;
+            if (new_geo) (void)hipFree(new_geo);
         }
         return s2;
     }
+    if (old_geo) (void)hipFree(old_geo);   // upload_levels synchronised the stream
     c->recon_pending = false;   // the state restarts
     c->camera = true;
     c->frames = 0;
@@ -752,6 +902,14 @@ sf_status sf_set_timing(sf_ctx c, int32_t enable) {
     return SF_OK;
 }
 
+sf_status sf_set_graph(sf_ctx c, int32_t enable) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!enable) drop_graphs(c);
+    c->graph_on = enable != 0;
+    return SF_OK;
+}
+
 sf_status sf_kernel_times(sf_ctx c, double* ms3, int64_t* launches3, int32_t reset) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
@@ -796,7 +954,7 @@ static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias
 }
 
 // network on the finest level of every stream, then the per-pixel choice, smoothing and store
-static sf_status run_learned(sf_ctx c, int q) {
+static sf_status run_learned(sf_ctx c, int q, hipStream_t strm) {
     const int P = c->segs.total;
     for (int l = 0; l < kCnnLayers; ++l) {
         ConvArgs a{};
@@ -808,7 +966,7 @@ static sf_status run_learned(sf_ctx c, int q) {
         a.nout = l < kCnnLayers - 1 ? 16 : 3;
         a.out = c->act[(l + 1) & 1];
         a.out_f32 = c->lbuf + (size_t)kLearnOut * P;
-        HIP_TRY(c, launch_conv(a, l == kCnnLayers - 1, c->stream));
+        HIP_TRY(c, launch_conv(a, l == kCnnLayers - 1, strm));
     }
     CombineArgs cb{};
     cb.lv = c->lv_dev;
@@ -822,10 +980,9 @@ static sf_status run_learned(sf_ctx c, int q) {
         cb.blk[cb.n] = b;
         b += ((L.rows + 31) / 32) * ((L.cols + 31) / 32);
         ++cb.n;
-        c->learned_pixels += (int64_t)L.rows * L.cols;
     }
     cb.blk[cb.n] = b;
-    HIP_TRY(c, launch_combine(c->storage, cb, c->stream));
+    HIP_TRY(c, launch_combine(c->storage, cb, strm));
     return SF_OK;
 }
 
@@ -842,6 +999,7 @@ sf_status sf_set_learned(sf_ctx c, const float* params, size_t n, float threshol
                               c->stream));
     HIP_TRY(c, launch_pack_weights(pack_args(c->params_dev, c->wf, c->wb, c->cnn_bias), c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);   // the threshold is an argument of a captured launch
     c->threshold = threshold;
     c->weights = true;
     return SF_OK;
@@ -889,7 +1047,179 @@ sf_status sf_get_update_inputs(sf_ctx c, int32_t stream, float* out) {
 }
 
 // -- frames ---------------------------------------------------------------------------------
-sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho, const double* dt) {
+// The pyramid launches of a frame on stream strm: finest to coarsest, one launch per two depths
+// (d, d + 1) for all streams.  With `rec`, the launches that read the frame's inputs are noted
+// (for a frame graph's node updates).
+static sf_status enqueue_pyramid(sf_ctx c, const FrameInputs& in, hipStream_t strm,
+                                 std::vector<sf_ctx_s::FrameArgsNode>* rec) {
+    for (int h = 1; h < c->max_levels; h += 2) {
+        const int tile = big_tile(c, h, 0);
+        ElemArgs a = tile_args(c, h, 0, 0, tile);
+        a.in = in;
+        if (a.n == 0) continue;
+        if (rec) {
+            rec->emplace_back();
+            rec->back().kind = 1;
+            rec->back().e = a;
+        }
+        TimedLaunch t(c, 0);
+        HIP_TRY(c, launch_pyramid(c->storage, tile, a, strm));
+        t.done();
+    }
+    return SF_OK;
+}
+
+// Every launch of a frame after the first on stream strm: the pyramid, the level-step launches
+// (reading the state of `parity`), the learned update, and the reconstruction of all but the
+// finest pair of levels (that one waits: recon_pending).
+static sf_status enqueue_frame(sf_ctx c, const FrameInputs& in, bool inertial,
+                               const Inertial* imu, int parity, hipStream_t strm,
+                               std::vector<sf_ctx_s::FrameArgsNode>* rec) {
+    sf_status st = enqueue_pyramid(c, in, strm, rec);
+    if (st != SF_OK) return st;
+    for (const auto& sl : c->step_launches) {
+        StepArgs a{};
+        a.lv = c->sv_dev + sl.e0;
+        a.nent = sl.n;
+        a.parity = parity;
+        a.in = in;
+        if (inertial) memcpy(a.imu, imu, sizeof a.imu);
+        if (rec) {
+            rec->emplace_back();
+            rec->back().kind = 2;
+            rec->back().st = a;
+        }
+        TimedLaunch t(c, 1);
+        HIP_TRY(c, launch_step(c->storage, inertial, c->grid, a, sl.nblocks, c->lds_bytes, strm));
+        t.done();
+    }
+    const int q = 1 - parity;
+    if (c->learned) {
+        st = run_learned(c, q, strm);
+        if (st != SF_OK) return st;
+    }
+    // reconstruction, coarse to fine: one launch per two levels (h + 1, h), h even, for the
+    // streams where h is below the top (the launch holding level 0 is deferred)
+    for (int h = (c->max_levels - 2) & ~1; h > 0; h -= 2) {
+        const int tile = recon_tile(c, h);
+        ElemArgs r = tile_args(c, h, 1, q, tile);
+        TimedLaunch t(c, 2);
+        HIP_TRY(c, launch_reconstruct(c->storage, tile, r, strm));
+        t.done();
+    }
+    return SF_OK;
+}
+
+// Releases the frame graphs (after the work already launched from them has finished).
+static void drop_graphs(sf_ctx c) {
+    bool any = false;
+    for (auto& byp : c->graphs)
+        for (auto& fg : byp) any = any || fg.x || fg.g;
+    if (!any) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& byp : c->graphs)
+        for (auto& fg : byp) {
+            if (fg.x) (void)hipGraphExecDestroy(fg.x);
+            if (fg.g) (void)hipGraphDestroy(fg.g);
+            fg = sf_ctx_s::FrameGraph{};
+        }
+}
+
+// Captures the frame's launches into the graph for (parity, inertial) on the private stream and
+// finds, in launch order, the kernel nodes whose arguments change from frame to frame.
+static sf_status capture_frame(sf_ctx c, sf_ctx_s::FrameGraph& fg, const FrameInputs& in,
+                               bool inertial, const Inertial* imu) {
+    if (!c->cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    std::vector<sf_ctx_s::FrameArgsNode> rec;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    sf_status st = enqueue_frame(c, in, inertial, imu, c->parity, c->cap, &rec);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (st != SF_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != SF_OK ? st : hip_fail(c, e, "hipStreamEndCapture");
+    }
+    // the capture on one stream is a chain: walk it from its root
+    std::vector<hipGraphNode_t> order;
+    size_t nroot = 0;
+    e = hipGraphGetRootNodes(g, nullptr, &nroot);
+    if (e == hipSuccess && nroot == 1) {
+        hipGraphNode_t n = nullptr;
+        e = hipGraphGetRootNodes(g, &n, &nroot);
+        while (e == hipSuccess && n) {
+            order.push_back(n);
+            size_t nd = 0;
+            e = hipGraphNodeGetDependentNodes(n, nullptr, &nd);
+            if (e != hipSuccess || nd == 0) break;
+            if (nd != 1) { e = hipErrorInvalidValue; break; }
+            e = hipGraphNodeGetDependentNodes(n, &n, &nd);
+        }
+    } else if (e == hipSuccess) {
+        e = hipErrorInvalidValue;
+    }
+    size_t k = 0;
+    for (size_t i = 0; e == hipSuccess && i < order.size(); ++i) {
+        hipGraphNodeType t;
+        e = hipGraphNodeGetType(order[i], &t);
+        if (e != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams p{};
+        e = hipGraphKernelNodeGetParams(order[i], &p);
+        if (e != hipSuccess) break;
+        const int kind = frame_input_kind(p.func);
+        if (kind == 0) continue;
+        if (k >= rec.size() || rec[k].kind != kind) { e = hipErrorInvalidValue; break; }
+        rec[k].node = order[i];
+        rec[k].p = p;
+        ++k;
+    }
+    if (e == hipSuccess && k != rec.size()) e = hipErrorInvalidValue;
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(c, e, "capturing the frame graph");
+    }
+    fg.g = g;
+    fg.x = x;
+    fg.nodes = std::move(rec);
+    return SF_OK;
+}
+
+// A frame after the first through the frame graph of the current parity: captured on first
+// use, then its pyramid and level-step nodes take this frame's inputs and it is launched on the
+// context stream.
+static sf_status replay_frame(sf_ctx c, const FrameInputs& in, bool inertial,
+                              const Inertial* imu) {
+    sf_ctx_s::FrameGraph& fg = c->graphs[c->parity][inertial ? 1 : 0];
+    if (!fg.x) {
+        sf_status st = capture_frame(c, fg, in, inertial, imu);
+        if (st != SF_OK) return st;
+    }
+    for (auto& nd : fg.nodes) {
+        void* args[1];
+        if (nd.kind == 1) {
+            nd.e.in = in;
+            args[0] = &nd.e;
+        } else {
+            nd.st.in = in;
+            if (inertial) memcpy(nd.st.imu, imu, sizeof nd.st.imu);
+            args[0] = &nd.st;
+        }
+        hipKernelNodeParams p = nd.p;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        HIP_TRY(c, hipGraphExecKernelNodeSetParams(fg.x, nd.node, &p));
+    }
+    HIP_TRY(c, hipGraphLaunch(fg.x, c->stream));
+    return SF_OK;
+}
+
+// A frame of every stream; omega, omega_dot and acc (host, 3 values per stream, or NULL for
+// zeros) are the camera rates of the inertial source terms, or all NULL for the paper's
+// prediction.
+static sf_status push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
+                             const double* dt, const double* omega, const double* omega_dot,
+                             const double* acc) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
     if (!c->camera) return fail(c, SF_ERR_STATE, "the cameras must be set before pushing");
@@ -901,6 +1231,11 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
             return fail(c, SF_ERR_INVALID_ARG, "stream %d: Y and rho must be device pointers", s);
         if (!(dt[s] > 0.0) || !isfinite(dt[s]))
             return fail(c, SF_ERR_INVALID_ARG, "stream %d: dt must be > 0 and finite", s);
+        for (int k = 0; k < 3; ++k)
+            if ((omega && !isfinite(omega[3 * s + k])) || (acc && !isfinite(acc[3 * s + k])) ||
+                (omega_dot && !isfinite(omega_dot[3 * s + k])))
+                return fail(c, SF_ERR_INVALID_ARG,
+                            "stream %d: omega, omega_dot and acc must be finite", s);
     }
     st = flush_recon(c);
     if (st != SF_OK) return st;
@@ -911,16 +1246,9 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         const double dp = c->st[s].dt_prev;
         in.scale[s] = (c->frames == 0 || dt[s] == dp) ? 1.0f : (float)(dt[s] / dp);
     }
-    // pyramid, finest to coarsest: one launch per two depths (d, d + 1) for all streams
-    for (int h = 1; h < c->max_levels; h += 2) {
-        const int tile = big_tile(c, h, 0);
-        ElemArgs a = tile_args(c, h, 0, 0, tile);
-        a.in = in;
-        TimedLaunch t(c, 0);
-        HIP_TRY(c, launch_pyramid(c->storage, tile, a, c->stream));
-        t.done();
-    }
     if (c->frames == 0) {
+        st = enqueue_pyramid(c, in, c->stream, nullptr);
+        if (st != SF_OK) return st;
         for (int h = 0; h < c->max_levels; ++h) {
             ElemArgs a = elem_args(c, h, 0);
             a.in = in;
@@ -928,33 +1256,37 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
         }
         c->parity = 0;
     } else {
-        for (const auto& sl : c->step_launches) {
-            StepArgs a{};
-            a.lv = c->sv_dev + sl.e0;
-            a.nent = sl.n;
-            a.parity = c->parity;
-            a.in = in;
-            TimedLaunch t(c, 1);
-            HIP_TRY(c, launch_step(c->storage, a, sl.nblocks, c->lds_bytes, c->stream));
-            t.done();
+        // inertial rates in the filter's time unit: Omega dt (rad/frame), dOmega dt^2
+        // (rad/frame^2), a dt^2 (1/frame^2)
+        Inertial imu[kMaxStreams] = {};
+        const bool inertial = omega || omega_dot || acc;
+        for (int s = 0; inertial && s < c->S; ++s) {
+            const double d = dt[s];
+            auto v = [&](const double* base, int k, double scale) {
+                return base ? (float)(base[3 * s + k] * scale) : 0.0f;
+            };
+            imu[s].ox = v(omega, 0, d);
+            imu[s].oy = v(omega, 1, d);
+            imu[s].oz = v(omega, 2, d);
+            imu[s].dx = v(omega_dot, 0, d * d);
+            imu[s].dy = v(omega_dot, 1, d * d);
+            imu[s].dz = v(omega_dot, 2, d * d);
+            imu[s].ax = v(acc, 0, d * d);
+            imu[s].ay = v(acc, 1, d * d);
+            imu[s].az = v(acc, 2, d * d);
         }
-        const int q = 1 - c->parity;
-        if (c->learned) {
-            sf_status s2 = run_learned(c, q);
-            if (s2 != SF_OK) return s2;
-        }
-        // reconstruction, coarse to fine: one launch per two levels (h + 1, h), h even, for
-        // the streams where h is below the top
-        // (the launch holding level 0 is deferred: recon_pending)
-        for (int h = (c->max_levels - 2) & ~1; h > 0; h -= 2) {
-            const int tile = recon_tile(c, h);
-            ElemArgs r = tile_args(c, h, 1, q, tile);
-            TimedLaunch t(c, 2);
-            HIP_TRY(c, launch_reconstruct(c->storage, tile, r, c->stream));
-            t.done();
-        }
+        if (c->graph_on && !c->timing)
+            st = replay_frame(c, in, inertial, imu);
+        else
+            st = enqueue_frame(c, in, inertial, imu, c->parity, c->stream, nullptr);
+        if (st != SF_OK) return st;
+        if (c->learned)
+            for (int s = 0; s < c->S; ++s) {
+                const LevelDev& L = c->lv[c->st[s].e0];
+                c->learned_pixels += (int64_t)L.rows * L.cols;
+            }
         c->recon_pending = c->max_levels >= 2;
-        c->parity = q;
+        c->parity = 1 - c->parity;
         for (int s = 0; s < c->S; ++s) c->st[s].update_ran = true;
     }
     for (int s = 0; s < c->S; ++s) c->st[s].dt_prev = dt[s];
@@ -962,11 +1294,29 @@ sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho,
     return SF_OK;
 }
 
+sf_status sf_push_frames(sf_ctx c, const void* const* Y, const void* const* rho, const double* dt) {
+    return push_frames(c, Y, rho, dt, nullptr, nullptr, nullptr);
+}
+
+sf_status sf_push_frames_ex(sf_ctx c, const void* const* Y, const void* const* rho,
+                            const double* dt, const double* omega, const double* omega_dot,
+                            const double* acc) {
+    return push_frames(c, Y, rho, dt, omega, omega_dot, acc);
+}
+
 sf_status sf_push_frame(sf_ctx c, const void* Y, const void* rho, double dt) {
     sf_status st = check_alive(c);
     if (st != SF_OK) return st;
     if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_push_frames");
-    return sf_push_frames(c, &Y, &rho, &dt);
+    return push_frames(c, &Y, &rho, &dt, nullptr, nullptr, nullptr);
+}
+
+sf_status sf_push_frame_ex(sf_ctx c, const void* Y, const void* rho, double dt,
+                           const double* omega, const double* omega_dot, const double* acc) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_push_frames_ex");
+    return push_frames(c, &Y, &rho, &dt, omega, omega_dot, acc);
 }
 
 // Outputs of the streams s with outs[s] set.  With the finest reconstruction pending (and a
@@ -1292,6 +1642,9 @@ sf_status sf_destroy(sf_ctx c) {
     if (c->lbuf) (void)hipFree(c->lbuf);
     if (c->mid) (void)hipFree(c->mid);
     if (c->sv_dev) (void)hipFree(c->sv_dev);
+    if (c->geo) (void)hipFree(c->geo);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     return SF_OK;
 }

@@ -73,6 +73,10 @@ struct LevelDev {
     // The prediction of a level may be split over several step launches ("passes") of at most
     // a few steps each, so that each pass needs a smaller halo.  A pass entry is a copy of its
     // level's entry with its own halo and tiles, and:
+    // General grids of directions: 9 planes of rows x gpitch floats (b1/dmu (3), b2/dmu (3),
+    // eta (3)), or NULL for the pinhole grid of the intrinsics above
+    const float* geo;
+    int gpitch;
     int pass_n;                      // steps of this pass (N, the level's steps, sets dt)
     int pass_first;                  // 1: loads the frame-k state (and applies the dt rescale)
     int pass_last;                   // 1: runs the update, smoothing and state store
@@ -88,11 +92,20 @@ struct FrameInputs {
     float scale[kMaxStreams];
 };
 
+// Camera rates of one stream for the inertial source terms of the prediction, in the filter's
+// time unit: angular velocity Omega (rad/frame), its rate of change dOmega (rad/frame^2) and
+// linear acceleration a (1/frame^2; times an inverse depth it is a structure-flow rate
+// change), all in the camera frame.
+struct Inertial {
+    float ox, oy, oz, dx, dy, dz, ax, ay, az;
+};
+
 struct StepArgs {
     const LevelDev* lv;              // the pass entries of this launch
     int nent;                        // entries; entry e owns blocks [lv[e].block0, lv[e+1].block0)
     int parity;                      // state[parity] is frame k, state[1 - parity] receives k+1
     FrameInputs in;
+    Inertial imu[kMaxStreams];       // read by the inertial form of the kernel only
 };
 
 // A launch of a per-pixel kernel over a list of entries: entry ent[k] owns blocks
@@ -121,14 +134,20 @@ hipError_t dev_malloc(void** p, size_t bytes);
 // tile: kTile2 or 2 kTile2 (the blocks in a.blk count tiles of that size)
 hipError_t launch_pyramid(int storage, int tile, const ElemArgs& a, hipStream_t s);
 hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s);
-hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds_bytes,
-                       hipStream_t s);
+// inertial: the prediction keeps the inertial source terms with the rates in a.imu;
+// grid: the levels' geometry comes from their tables (LevelDev::geo), not the pinhole
+hipError_t launch_step(int storage, bool inertial, bool grid, const StepArgs& a, int nblocks,
+                       size_t lds_bytes, hipStream_t s);
 // tile: kTile2 (one level-h pixel per thread) or 2 kTile2 (four); the blocks in a.blk count
 // tiles of that size
 hipError_t launch_reconstruct(int storage, int tile, const ElemArgs& a, hipStream_t s);
 hipError_t launch_output(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t launch_learned_extract(int storage, const ElemArgs& a, hipStream_t s);
 hipError_t prepare_kernels(size_t max_lds_bytes);
+// Which per-frame arguments a kernel of this library reads, for updating the kernel nodes of a
+// captured frame graph: 1 = ElemArgs::in (the pyramid), 2 = StepArgs::in and ::imu (the level
+// step), 0 = none (the other kernels' arguments do not change from frame to frame).
+int frame_input_kind(const void* func);
 
 // learned update: choose between the network's and the least-squares solution per pixel,
 // smooth, store the finest level's new flow state (one launch for all streams)

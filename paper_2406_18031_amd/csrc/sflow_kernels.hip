@@ -83,8 +83,14 @@ __device__ __forceinline__ Geo pixel_geo(ConstLevelDev& L, int i, int j) {
     return g;
 }
 
-// dmu = sqrt(1 - eta_x^2) / (fx |r_n|), computed as in the update stage of k_step
+// dmu = sqrt(1 - eta_x^2) / (fx |r_n|), computed as in the update stage of k_step; on a general
+// grid 1 / |b1/dmu| from the level's geometry table, as there
 __device__ __forceinline__ float pixel_dmu(ConstLevelDev& L, int i, int j) {
+    if (L.geo) {
+        const size_t plane = (size_t)L.rows * L.gpitch, o = (size_t)i * L.gpitch + j;
+        const float a = L.geo[o], b = L.geo[plane + o], c = L.geo[2 * plane + o];
+        return rsqrtf(fmaf(a, a, fmaf(b, b, c * c)));
+    }
     const float x = fmaf((float)j, L.ifx, -L.cxn);
     const float xn = x + (j < L.cols - 1 ? L.ifx : -L.ifx);
     const float y = fmaf((float)i, L.ify, -L.cyn);
@@ -207,27 +213,154 @@ __device__ __forceinline__ void row_geo(ConstLevelDev& L, int i, float x, float 
 constexpr int kNW = kBlock / 64;        // waves per block
 constexpr int kRPW = kRegion / kNW;     // region rows per wave
 
+// Geometry of the pixels a lane holds in the fused level kernel (its column, the wave's kRPW
+// rows and the rows just above and below the strip), giving for a flow w the column and row
+// optical flow u = b1.w / dmu, v = b2.w / dmu (eq:oflow_numeric), the normal component
+// s = <eta, w>, and for the update the frame (eta, b1, b2, dmu).
+//
+// Pinhole grid: closed forms from the intrinsics (see pixel_geo), nothing read from memory.
+struct PinholeRows {
+    static constexpr bool kB2xZero = true;   // b2 has no x component
+    float x, xn;
+    float y[kRPW], rinv[kRPW], fxrn[kRPW], xi[kRPW], B[kRPW];
+    float yA, BA, yBl, BBl;   // rows just above / below the strip (y and B)
+    __device__ __forceinline__ void load(ConstLevelDev& L, int wi0, int j) {
+        x = fmaf((float)j, L.ifx, -L.cxn);
+        xn = x + (j < L.cols - 1 ? L.ifx : -L.ifx);
+#pragma unroll
+        for (int r = 0; r < kRPW; ++r) row_geo(L, wi0 + r, x, xn, y[r], rinv[r], fxrn[r], xi[r], B[r]);
+        // same arithmetic as the owning wave, so results do not depend on where strips start
+        float t0, t1, t2;
+        row_geo(L, wi0 - 1, x, xn, yA, t0, t1, t2, BA);
+        row_geo(L, wi0 + kRPW, x, xn, yBl, t0, t1, t2, BBl);
+    }
+    __device__ __forceinline__ void us(int r, float wx, float wy, float wz, float& u,
+                                       float& s) const {
+        const float t = fmaf(y[r], wy, wz);
+        u = fxrn[r] * fmaf(-xi[r], t, wx);      // b1.w / dmu
+        s = rinv[r] * fmaf(x, wx, t);           // <eta, w>
+    }
+    __device__ __forceinline__ float v(int r, float wx, float wy, float wz) const {
+        (void)wx;
+        return B[r] * fmaf(-y[r], wz, wy);
+    }
+    __device__ __forceinline__ float v_above(float wx, float wy, float wz) const {
+        (void)wx;
+        return BA * fmaf(-yA, wz, wy);
+    }
+    __device__ __forceinline__ float v_below(float wx, float wy, float wz) const {
+        (void)wx;
+        return BBl * fmaf(-yBl, wz, wy);
+    }
+    __device__ __forceinline__ float s(int r, float wx, float wy, float wz) const {
+        return rinv[r] * fmaf(x, wx, fmaf(y[r], wy, wz));
+    }
+    __device__ __forceinline__ void eta(int r, float& ex, float& ey, float& ez) const {
+        ex = x * rinv[r];
+        ey = y[r] * rinv[r];
+        ez = rinv[r];
+    }
+    // tangent frame: b1 = (e_x - eta eta_x)/q, b2 = (0, eta_z, -eta_y)/q with q = sqrt(1 - eta_x^2)
+    __device__ __forceinline__ void frame(int r, float (&e)[3], float (&b1)[3], float (&b2)[3],
+                                          float& dmu, float& idmu) const {
+        eta(r, e[0], e[1], e[2]);
+        const float q = __builtin_amdgcn_sqrtf(fmaf(y[r], y[r], 1.0f)) * rinv[r];
+        const float iq = __builtin_amdgcn_rcpf(q);
+        b1[0] = q;
+        b1[1] = -e[0] * e[1] * iq;
+        b1[2] = -e[0] * e[2] * iq;
+        b2[0] = 0.0f;
+        b2[1] = e[2] * iq;
+        b2[2] = -e[1] * iq;
+        dmu = q * __builtin_amdgcn_rcpf(fxrn[r]);
+        idmu = fxrn[r] * iq;
+    }
+};
+
+// General grid of unit directions: per pixel b1/dmu, b2/dmu and eta from the level's geometry
+// table (9 planes, written at set-up from the caller's grid).  Rows outside the level read the
+// nearest row (clamped), lanes outside it column 0: their values only reach pixels outside the
+// valid band.
+struct GridRows {
+    static constexpr bool kB2xZero = false;
+    float g1[kRPW][3], g2[kRPW][3], e[kRPW][3];
+    float g2A[3], g2B[3];
+    __device__ __forceinline__ void load(ConstLevelDev& L, int wi0, int j) {
+        const int jc = clampi(j, 0, L.cols - 1);
+        const size_t plane = (size_t)L.rows * L.gpitch;
+#pragma unroll
+        for (int r = 0; r < kRPW; ++r) {
+            const size_t o = (size_t)clampi(wi0 + r, 0, L.rows - 1) * L.gpitch + jc;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                g1[r][k] = L.geo[k * plane + o];
+                g2[r][k] = L.geo[(3 + k) * plane + o];
+                e[r][k] = L.geo[(6 + k) * plane + o];
+            }
+        }
+        const size_t oA = (size_t)clampi(wi0 - 1, 0, L.rows - 1) * L.gpitch + jc;
+        const size_t oB = (size_t)clampi(wi0 + kRPW, 0, L.rows - 1) * L.gpitch + jc;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            g2A[k] = L.geo[(3 + k) * plane + oA];
+            g2B[k] = L.geo[(3 + k) * plane + oB];
+        }
+    }
+    __device__ __forceinline__ void us(int r, float wx, float wy, float wz, float& u,
+                                       float& s_) const {
+        u = fmaf(g1[r][0], wx, fmaf(g1[r][1], wy, g1[r][2] * wz));
+        s_ = fmaf(e[r][0], wx, fmaf(e[r][1], wy, e[r][2] * wz));
+    }
+    __device__ __forceinline__ float v(int r, float wx, float wy, float wz) const {
+        return fmaf(g2[r][0], wx, fmaf(g2[r][1], wy, g2[r][2] * wz));
+    }
+    __device__ __forceinline__ float v_above(float wx, float wy, float wz) const {
+        return fmaf(g2A[0], wx, fmaf(g2A[1], wy, g2A[2] * wz));
+    }
+    __device__ __forceinline__ float v_below(float wx, float wy, float wz) const {
+        return fmaf(g2B[0], wx, fmaf(g2B[1], wy, g2B[2] * wz));
+    }
+    __device__ __forceinline__ float s(int r, float wx, float wy, float wz) const {
+        return fmaf(e[r][0], wx, fmaf(e[r][1], wy, e[r][2] * wz));
+    }
+    __device__ __forceinline__ void eta(int r, float& ex, float& ey, float& ez) const {
+        ex = e[r][0];
+        ey = e[r][1];
+        ez = e[r][2];
+    }
+    // |b1/dmu| = 1/dmu; b1, b2 are the table's vectors times dmu
+    __device__ __forceinline__ void frame(int r, float (&ee)[3], float (&b1)[3], float (&b2)[3],
+                                          float& dmu, float& idmu) const {
+        eta(r, ee[0], ee[1], ee[2]);
+        const float n2 = fmaf(g1[r][0], g1[r][0], fmaf(g1[r][1], g1[r][1], g1[r][2] * g1[r][2]));
+        dmu = rsqrtf(n2);
+        idmu = n2 * dmu;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            b1[k] = g1[r][k] * dmu;
+            b2[k] = g2[r][k] * dmu;
+        }
+    }
+};
+
 // One column (beta_1) half-step of every row held by this wave.  Rows outside the image or
 // outside the band still valid after the previous steps are stepped too (their values are
 // finite and reach only rows that leave the valid band themselves), so every field is updated
 // in place with no per-row branch.
-template <int NF, bool BORDER>
-__device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&grinv)[kRPW],
-                                            const float (&gfxrn)[kRPW], const float (&gxi)[kRPW],
-                                            const float (&gy)[kRPW], float x, bool at_left,
+template <int NF, bool BORDER, class G>
+__device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const G& geo, bool at_left,
                                             bool at_right, float dt, float lim, float dtsig,
                                             bool dom_lit) {
 #pragma unroll
     for (int r = 0; r < kRPW; ++r) {
         const float wx = F[r][0], wy = F[r][1], wz = F[r][2];
-        const float t = fmaf(gy[r], wy, wz);
-        const float u = gfxrn[r] * fmaf(-gxi[r], t, wx);      // b1.w / dmu
+        float u, s;
+        geo.us(r, wx, wy, wz, u, s);                          // b1.w / dmu, <eta, w>
         const float um = nb_prev<BORDER>(u, at_left);
         const float up = nb_next<BORDER>(u, at_right);
         const bool larger_next = fabsf(up) > fabsf(um);
         float uh = dom_lit ? (larger_next ? um : up) : (larger_next ? up : um);
         uh = __builtin_amdgcn_fmed3f(uh, -lim, lim);         // stability bound (lim = N or inf)
-        const float s = grinv[r] * fmaf(x, wx, t);           // <eta, w>
         // upwind step f - dt (u_hat D f + sigma s f) with D the one-sided difference toward
         // the upwind side, written as k0 f + ap f_left - am f_right with ap = dt max(u_hat, 0),
         // am = dt min(u_hat, 0), k0 = 1 - dt sigma s - ap + am (no source term for the image).
@@ -264,19 +397,16 @@ __device__ __forceinline__ void column_pass(float (&F)[kRPW][NF], const float (&
 // own registers and, for its first and last rows, the rows above and below the strip (from
 // the neighbouring waves).  Same upwind form as the column pass; at the image's first and last
 // row the missing neighbour's coefficient is dropped.
-template <int NF, bool TOP>
+template <int NF, bool TOP, class G>
 __device__ __forceinline__ void row_pass(float (&F)[kRPW][NF], const float (&above)[NF],
-                                         const float (&below)[NF], const float (&grinv)[kRPW],
-                                         const float (&gy)[kRPW], const float (&gB)[kRPW],
-                                         float x, float yA, float BA, float yBl, float BBl,
-                                         int wi0, int R, float dt, float lim, float dtsig,
-                                         bool dom_lit) {
+                                         const float (&below)[NF], const G& geo, int wi0, int R,
+                                         float dt, float lim, float dtsig, bool dom_lit) {
     constexpr int RPW = kRPW;
     float v[RPW];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) v[r] = gB[r] * fmaf(-gy[r], F[r][2], F[r][1]);
-    const float vA = BA * fmaf(-yA, above[2], above[1]);
-    const float vB = BBl * fmaf(-yBl, below[2], below[1]);
+    for (int r = 0; r < RPW; ++r) v[r] = geo.v(r, F[r][0], F[r][1], F[r][2]);
+    const float vA = geo.v_above(above[0], above[1], above[2]);
+    const float vB = geo.v_below(below[0], below[1], below[2]);
     float prev[NF];
 #pragma unroll
     for (int k = 0; k < NF; ++k) prev[k] = above[k];
@@ -294,7 +424,7 @@ __device__ __forceinline__ void row_pass(float (&F)[kRPW][NF], const float (&abo
         const bool larger_next = fabsf(vp) > fabsf(vm);
         float vh = dom_lit ? (larger_next ? vm : vp) : (larger_next ? vp : vm);
         vh = __builtin_amdgcn_fmed3f(vh, -lim, lim);
-        const float s = grinv[r] * fmaf(x, cur[0], fmaf(gy[r], cur[1], cur[2]));
+        const float s = geo.s(r, cur[0], cur[1], cur[2]);
         const float dv = dt * vh;
         const float ap = top_b ? 0.0f : fmaxf(dv, 0.0f);
         const float am = bot_b ? 0.0f : fminf(dv, 0.0f);
@@ -312,6 +442,47 @@ __device__ __forceinline__ void row_pass(float (&F)[kRPW][NF], const float (&abo
 #pragma unroll
         for (int k = 0; k < NF; ++k) prev[k] = cur[k];
         vprev = vc;
+    }
+}
+
+// Inertial source terms of eq:hflow_conservation that eq:assumption drops, as an explicit step
+// of length dt after each column/row step of the prediction: with the camera's angular velocity
+// Omega, its rate of change dOmega and linear acceleration a (uniform; rad/frame, rad/frame^2
+// and 1/frame^2),
+//   w  += dt (-2 Omega x w - Omega x (Omega x eta) - dOmega x eta - rho a)
+//   dw += dt (-2 Omega x dw)                               (lower levels: the linear part)
+// where Omega x (Omega x eta) = Omega (Omega . eta) - eta |Omega|^2, the acceleration enters
+// with -rho a (from w = -Omega x eta - rho v and eq:camvel_dot), and -dOmega x eta is what a
+// changing rate adds to the derivative of -Omega x eta (the paper takes Omega constant).
+template <int NF, bool TOP, class G>
+__device__ __forceinline__ void inertial_step(float (&F)[kRPW][NF], const G& geo, float dt,
+                                              const Inertial& m) {
+    constexpr int KR = TOP ? 3 : 6;
+    const float oo = fmaf(m.ox, m.ox, fmaf(m.oy, m.oy, m.oz * m.oz));
+    const float m2 = -2.0f * dt;
+#pragma unroll
+    for (int r = 0; r < kRPW; ++r) {
+        float ex, ey, ez;
+        geo.eta(r, ex, ey, ez);
+        const float c = fmaf(m.ox, ex, fmaf(m.oy, ey, m.oz * ez));     // Omega . eta
+        const float rho = F[r][KR];
+        const float wx = F[r][0], wy = F[r][1], wz = F[r][2];
+        // -Omega x (Omega x eta) - dOmega x eta - rho a, per component
+        const float px = fmaf(m.dy, ez, fmaf(-m.dz, ey, rho * m.ax));   // (dOmega x eta) + rho a
+        const float py = fmaf(m.dz, ex, fmaf(-m.dx, ez, rho * m.ay));
+        const float pz = fmaf(m.dx, ey, fmaf(-m.dy, ex, rho * m.az));
+        const float qx = fmaf(ex, oo, -fmaf(m.ox, c, px));
+        const float qy = fmaf(ey, oo, -fmaf(m.oy, c, py));
+        const float qz = fmaf(ez, oo, -fmaf(m.oz, c, pz));
+        F[r][0] = fmaf(m2, fmaf(m.oy, wz, -m.oz * wy), fmaf(dt, qx, wx));
+        F[r][1] = fmaf(m2, fmaf(m.oz, wx, -m.ox * wz), fmaf(dt, qy, wy));
+        F[r][2] = fmaf(m2, fmaf(m.ox, wy, -m.oy * wx), fmaf(dt, qz, wz));
+        if constexpr (!TOP) {
+            const float dx = F[r][3], dy = F[r][4], dz = F[r][5];
+            F[r][3] = fmaf(m2, fmaf(m.oy, dz, -m.oz * dy), dx);
+            F[r][4] = fmaf(m2, fmaf(m.oz, dx, -m.ox * dz), dy);
+            F[r][5] = fmaf(m2, fmaf(m.ox, dy, -m.oy * dx), dz);
+        }
     }
 }
 
@@ -395,7 +566,7 @@ __device__ __forceinline__ void smooth_passes(float (&F)[kRPW][NF], float* lds, 
     }
 }
 
-template <typename T, bool TOP>
+template <typename T, bool TOP, bool IMU, class G>
 __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, int h, int t,
                                            float* lds) {
     constexpr int NF = TOP ? 4 : 8;   // top: w(3), rho; lower: w(3), dw(3), rho, Yhat
@@ -422,21 +593,9 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
     // rows of the region held by this wave that lie in the image
     const int vi0 = max(gi0, 0), vi1 = min(gi0 + RH, R);
 
-    // ---- geometry of this lane's pixels (pinhole closed forms, see pixel_geo) -------------
-    const float x = fmaf((float)j, L.ifx, -L.cxn);
-    const float xn = x + (j < C - 1 ? L.ifx : -L.ifx);
-    float grinv[RPW], gfxrn[RPW], gxi[RPW], gB[RPW], gy[RPW];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r)
-        row_geo(L, wi0 + r, x, xn, gy[r], grinv[r], gfxrn[r], gxi[r], gB[r]);
-    // rows just above and below this wave's strip, for the row-pass halo (same arithmetic as
-    // the owning wave, so results do not depend on where strips start)
-    float yA, BA, yBl, BBl;
-    {
-        float t0, t1, t2;
-        row_geo(L, wi0 - 1, x, xn, yA, t0, t1, t2, BA);
-        row_geo(L, wi0 + RPW, x, xn, yBl, t0, t1, t2, BBl);
-    }
+    // ---- geometry of this lane's pixels and of the rows just above and below the strip -------
+    G geo;
+    geo.load(L, wi0, j);
 
     // ---- load the frame-k state of the region into registers ------------------------------
     // Every load is issued unconditionally, from an address clamped into the plane (pixel 0 for
@@ -518,11 +677,9 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
     for (int n = 0; n < L.pass_n; ++n) {   // the steps of this pass
         // column half-step: neighbours from adjacent lanes
         if (border)
-            column_pass<NF, true>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, lim, dtsig,
-                                  dom_lit);
+            column_pass<NF, true>(F, geo, at_left, at_right, dt, lim, dtsig, dom_lit);
         else
-            column_pass<NF, false>(F, grinv, gfxrn, gxi, gy, x, at_left, at_right, dt, lim, dtsig,
-                                   dom_lit);
+            column_pass<NF, false>(F, geo, at_left, at_right, dt, lim, dtsig, dom_lit);
         // row half-step: neighbours from the rows above/below, across waves through LDS
         float* xb = XB + (n & 1) * (NW * 2 * NF * 64);
 #pragma unroll
@@ -540,8 +697,8 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
             above[k] = xb[((wa * 2 + 1) * NF + k) * 64 + lane];
             below[k] = xb[((wb * 2 + 0) * NF + k) * 64 + lane];
         }
-        row_pass<NF, TOP>(F, above, below, grinv, gy, gB, x, yA, BA, yBl, BBl, wi0, R, dt, lim,
-                          dtsig, dom_lit);
+        row_pass<NF, TOP>(F, above, below, geo, wi0, R, dt, lim, dtsig, dom_lit);
+        if constexpr (IMU) inertial_step<NF, TOP>(F, geo, dt, a.imu[L.stream]);
     }
     __syncthreads();   // the LDS below is reused for the update phase
 
@@ -631,27 +788,24 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
                 r2 = minabs_diff(rc, rpre[r + 2], rpre[r]);
             }
             // tangent basis and spacing at (i, j)
-            const float rinv = grinv[r];
-            const float ex = x * rinv, ey = gy[r] * rinv, ez = rinv;
-            const float q = __builtin_amdgcn_sqrtf(fmaf(gy[r], gy[r], 1.0f)) * rinv;   // sqrt(1 - eta_x^2)
-            const float iq = __builtin_amdgcn_rcpf(q);
-            const float b1x = q, b1y = -ex * ey * iq, b1z = -ex * ez * iq;
-            const float b2y = ez * iq, b2z = -ey * iq;
-            const float dmu = q * __builtin_amdgcn_rcpf(gfxrn[r]);
-            const float aYx = b1x * d1, aYy = fmaf(b1y, d1, b2y * d2), aYz = fmaf(b1z, d1, b2z * d2);
+            float ee[3], b1[3], b2[3], dmu, idmu;
+            geo.frame(r, ee, b1, b2, dmu, idmu);
+            const float ex = ee[0], ey = ee[1], ez = ee[2];
+            // 2-D gradients to 3-D: B (d1, d2) (b2's x component is 0 on a pinhole grid)
+            const float aYx = G::kB2xZero ? b1[0] * d1 : fmaf(b1[0], d1, b2[0] * d2);
+            const float aYy = fmaf(b1[1], d1, b2[1] * d2), aYz = fmaf(b1[2], d1, b2[2] * d2);
             float aRx = 0.0f, aRy = 0.0f, aRz = 0.0f, cR = 0.0f;
             const size_t gs = (size_t)i * L.pitch + j;
             const float rprior = TOP ? ldv(Rold, gs) : F[r][KR];
             const float Yprior = TOP ? ldv(Yold, gs) : F[r][7 % NF];
             if (rv) {
                 const float kk = dmu * rc;
-                aRx = fmaf(kk, ex, b1x * r1);
-                aRy = fmaf(kk, ey, fmaf(b1y, r1, b2y * r2));
-                aRz = fmaf(kk, ez, fmaf(b1z, r1, b2z * r2));
+                aRx = fmaf(kk, ex, G::kB2xZero ? b1[0] * r1 : fmaf(b1[0], r1, b2[0] * r2));
+                aRy = fmaf(kk, ey, fmaf(b1[1], r1, b2[1] * r2));
+                aRz = fmaf(kk, ez, fmaf(b1[2], r1, b2[2] * r2));
                 cR = rc - rprior;
             }
             const float cY = Yh - Yprior;
-            const float idmu = gfxrn[r] * iq;
             constexpr int KX = TOP ? 0 : 3;
             const float x0 = F[r][KX] * idmu, y0 = F[r][KX + 1] * idmu, z0 = F[r][KX + 2] * idmu;
             const float dmu2 = dmu * dmu;
@@ -757,7 +911,7 @@ __device__ __forceinline__ int xcd_local_block(int w, int n) {
     return ((k / g) * kXcds + x) * g + k % g;
 }
 
-template <typename T>
+template <typename T, bool IMU, class G>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     extern __shared__ float lds[];
     const int b = xcd_local_block(blockIdx.x, gridDim.x);
@@ -769,9 +923,9 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs a) {
     }
     ConstLevelDev& L = level_entry(a.lv, lo);
     if (L.top)
-        level_tile<T, true>(a, L, L.level, b - L.block0, lds);
+        level_tile<T, true, IMU, G>(a, L, L.level, b - L.block0, lds);
     else
-        level_tile<T, false>(a, L, L.level, b - L.block0, lds);
+        level_tile<T, false, IMU, G>(a, L, L.level, b - L.block0, lds);
 }
 
 // The entry and pixel of a per-pixel launch; false past the entry's last pixel.
@@ -992,6 +1146,18 @@ __device__ __forceinline__ void emit_flow(const ElemArgs& a, int k, ConstLevelDe
         out[o] = wx * m;
         out[o + plane] = wy * m;
         out[o + 2 * plane] = wz * m;
+        return;
+    }
+    if (L.geo) {   // general grid: (b1.w, b2.w) / dmu and <eta, w> / dmu from the table
+        const size_t gp = (size_t)L.rows * L.gpitch, go = (size_t)i * L.gpitch + j;
+        const float* G = L.geo + go;
+        if (a.kind == SF_FLOW_TANGENT_PX) {
+            out[o] = fmaf(G[0], wx, fmaf(G[gp], wy, G[2 * gp] * wz));
+            out[o + plane] = fmaf(G[3 * gp], wx, fmaf(G[4 * gp], wy, G[5 * gp] * wz));
+        } else {
+            const float n2 = fmaf(G[0], G[0], fmaf(G[gp], G[gp], G[2 * gp] * G[2 * gp]));
+            out[o] = fmaf(G[6 * gp], wx, fmaf(G[7 * gp], wy, G[8 * gp] * wz)) * sqrtf(n2);
+        }
         return;
     }
     const Geo g = pixel_geo(L, i, j);
@@ -1334,13 +1500,34 @@ __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
+// every instantiation of the level step: storage x inertial terms x grid
+#define SFLOW_STEP_KERNELS                                                                     \
+    (const void*)k_step<float, false, PinholeRows>, (const void*)k_step<__half, false, PinholeRows>, \
+    (const void*)k_step<float, true, PinholeRows>, (const void*)k_step<__half, true, PinholeRows>,   \
+    (const void*)k_step<float, false, GridRows>, (const void*)k_step<__half, false, GridRows>,       \
+    (const void*)k_step<float, true, GridRows>, (const void*)k_step<__half, true, GridRows>
+
+int frame_input_kind(const void* func) {
+    const void* step[] = {SFLOW_STEP_KERNELS};
+    const void* pyr[] = {(const void*)k_pyramid<float, kTile2>,
+                         (const void*)k_pyramid<__half, kTile2>,
+                         (const void*)k_pyramid<float, 2 * kTile2>,
+                         (const void*)k_pyramid<__half, 2 * kTile2>};
+    for (const void* f : step)
+        if (f == func) return 2;
+    for (const void* f : pyr)
+        if (f == func) return 1;
+    return 0;
+}
+
 hipError_t prepare_kernels(size_t max_lds_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_step<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)max_lds_bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_step<__half>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds_bytes);
+    const void* fns[] = {SFLOW_STEP_KERNELS};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)max_lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 static int elem_blocks(const ElemArgs& a) { return a.blk[a.n]; }
@@ -1371,11 +1558,29 @@ hipError_t launch_init(int storage, const ElemArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_step(int storage, const StepArgs& a, int nblocks, size_t lds, hipStream_t s) {
-    if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_step<__half>, dim3(nblocks), dim3(kBlock), lds, s, a);
+template <typename T, bool IMU>
+static void launch_step_g(bool grid, const StepArgs& a, dim3 g, dim3 b, size_t lds,
+                          hipStream_t s) {
+    if (grid)
+        hipLaunchKernelGGL((k_step<T, IMU, GridRows>), g, b, lds, s, a);
     else
-        hipLaunchKernelGGL(k_step<float>, dim3(nblocks), dim3(kBlock), lds, s, a);
+        hipLaunchKernelGGL((k_step<T, IMU, PinholeRows>), g, b, lds, s, a);
+}
+
+hipError_t launch_step(int storage, bool inertial, bool grid, const StepArgs& a, int nblocks,
+                       size_t lds, hipStream_t s) {
+    const dim3 g(nblocks), b(kBlock);
+    if (storage == SF_FP16) {
+        if (inertial)
+            launch_step_g<__half, true>(grid, a, g, b, lds, s);
+        else
+            launch_step_g<__half, false>(grid, a, g, b, lds, s);
+    } else {
+        if (inertial)
+            launch_step_g<float, true>(grid, a, g, b, lds, s);
+        else
+            launch_step_g<float, false>(grid, a, g, b, lds, s);
+    }
     return hipGetLastError();
 }
 

@@ -48,7 +48,15 @@ class sf_config(ctypes.Structure):
 
 class sf_camera(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
-                ("cy", ctypes.c_double)]
+                ("cy", ctypes.c_double), ("eta", ctypes.c_void_p)]
+
+
+def _camera(fx, fy, cx, cy, eta=None):
+    """An sf_camera and the array its eta points to (kept alive by the caller for the call)."""
+    if eta is None:
+        return sf_camera(fx, fy, cx, cy, None), None
+    a = np.ascontiguousarray(eta, dtype=np.float64)
+    return sf_camera(fx, fy, cx, cy, a.ctypes.data), a
 
 
 class SflowError(RuntimeError):
@@ -71,6 +79,9 @@ def _load():
         "sf_create": (st, [ctypes.POINTER(sf_config), vp, ctypes.POINTER(vp)]),
         "sf_set_camera": (st, [vp, ctypes.POINTER(sf_camera)]),
         "sf_push_frame": (st, [vp, vp, vp, ctypes.c_double]),
+        "sf_push_frame_ex": (st, [vp, vp, vp, ctypes.c_double, vp, vp, vp]),
+        "sf_push_frames_ex": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(ctypes.c_double), vp, vp, vp]),
         "sf_get_flow": (st, [vp, ctypes.c_int32, vp]),
         "sf_state_size": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
         "sf_get_state": (st, [vp, vp, ctypes.c_size_t]),
@@ -79,6 +90,8 @@ def _load():
         "sf_last_error": (ctypes.c_char_p, [vp]),
         "sf_set_tile": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "sf_set_timing": (st, [vp, ctypes.c_int32]),
+        "sf_set_graph": (st, [vp, ctypes.c_int32]),
+        "sf_copy_probe": (st, [vp, vp, ctypes.c_size_t, vp]),
         "sf_set_pass_steps": (st, [vp, ctypes.c_int32]),
         "sf_kernel_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
@@ -124,7 +137,8 @@ EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_st
             "sf_get_state_stream", "sf_set_state_stream", "sf_set_learned", "sf_learned_stats",
             "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
             "sf_net_forward", "sf_net_train_step", "sf_net_set_loss", "sf_net_destroy",
-            "sf_net_last_error", "sf_net_forward_noalloc")
+            "sf_net_last_error", "sf_net_forward_noalloc", "sf_push_frame_ex",
+            "sf_push_frames_ex", "sf_set_graph", "sf_copy_probe")
 
 
 def _check(status: int, ctx) -> None:
@@ -172,13 +186,31 @@ def sf_create(cfg: sf_config, stream=None) -> int:
     return out.value
 
 
-def sf_set_camera(ctx: int, fx: float, fy: float, cx: float, cy: float) -> None:
-    cam = sf_camera(fx, fy, cx, cy)
+def sf_set_camera(ctx: int, fx: float, fy: float, cx: float, cy: float, eta=None) -> None:
+    """eta: None (pinhole) or the finest level's unit directions, (rows, cols, 3)."""
+    cam, keep = _camera(fx, fy, cx, cy, eta)
     _check(lib.sf_set_camera(ctx, ctypes.byref(cam)), ctx)
+    del keep
 
 
 def sf_push_frame(ctx: int, Y, rho, dt: float) -> None:
     _check(lib.sf_push_frame(ctx, _ptr(Y), _ptr(rho), float(dt)), ctx)
+
+
+def _vec3s(v, n):
+    """None, or n 3-vectors as a flat ctypes double array."""
+    if v is None:
+        return None
+    a = np.asarray(v, dtype=np.float64).reshape(-1)
+    if a.size != 3 * n:
+        raise ValueError(f"expected {3 * n} values")
+    return (ctypes.c_double * a.size)(*a.tolist())
+
+
+def sf_push_frame_ex(ctx: int, Y, rho, dt: float, omega=None, omega_dot=None,
+                     acc=None) -> None:
+    _check(lib.sf_push_frame_ex(ctx, _ptr(Y), _ptr(rho), float(dt), _vec3s(omega, 1),
+                                _vec3s(omega_dot, 1), _vec3s(acc, 1)), ctx)
 
 
 def sf_get_flow(ctx: int, kind: int, out) -> None:
@@ -224,6 +256,16 @@ def sf_set_timing(ctx: int, enable: bool) -> None:
     _check(lib.sf_set_timing(ctx, 1 if enable else 0), ctx)
 
 
+def sf_copy_probe(src, dst, nbytes: int, stream=None) -> None:
+    st = lib.sf_copy_probe(_ptr(src), _ptr(dst), int(nbytes), _stream(stream))
+    if st != SF_OK:
+        raise SflowError(st, "sf_copy_probe")
+
+
+def sf_set_graph(ctx: int, enable: bool) -> None:
+    _check(lib.sf_set_graph(ctx, 1 if enable else 0), ctx)
+
+
 def sf_kernel_times(ctx: int, reset: bool = False):
     ms = (ctypes.c_double * 3)()
     n = (ctypes.c_int64 * 3)()
@@ -248,8 +290,11 @@ def sf_stream_count(ctx: int) -> int:
 
 
 def sf_set_cameras(ctx: int, cams: Sequence[Sequence[float]]) -> None:
-    arr = (sf_camera * len(cams))(*[sf_camera(*c) for c in cams])
+    """cams: per stream (fx, fy, cx, cy) or (fx, fy, cx, cy, eta)."""
+    made = [_camera(*c) for c in cams]
+    arr = (sf_camera * len(cams))(*[m[0] for m in made])
     _check(lib.sf_set_cameras(ctx, arr), ctx)
+    del made
 
 
 def sf_push_frames(ctx: int, Ys, rhos, dts) -> None:
@@ -258,6 +303,16 @@ def sf_push_frames(ctx: int, Ys, rhos, dts) -> None:
     r = (ctypes.c_void_p * n)(*[_ptr(t) for t in rhos])
     d = (ctypes.c_double * n)(*[float(v) for v in dts])
     _check(lib.sf_push_frames(ctx, y, r, d), ctx)
+
+
+def sf_push_frames_ex(ctx: int, Ys, rhos, dts, omegas=None, omega_dots=None,
+                      accs=None) -> None:
+    n = len(Ys)
+    y = (ctypes.c_void_p * n)(*[_ptr(t) for t in Ys])
+    r = (ctypes.c_void_p * n)(*[_ptr(t) for t in rhos])
+    d = (ctypes.c_double * n)(*[float(v) for v in dts])
+    _check(lib.sf_push_frames_ex(ctx, y, r, d, _vec3s(omegas, n), _vec3s(omega_dots, n),
+                                 _vec3s(accs, n)), ctx)
 
 
 def sf_get_flow_stream(ctx: int, stream: int, kind: int, out) -> None:
@@ -424,16 +479,19 @@ class Filter:
 
     def __init__(self, rows, cols, levels, max_flow_px, smooth_iters, fx, fy, cx, cy,
                  alpha=DEFAULT_ALPHA, storage=SF_FP32, read_flags=0, stream=None,
-                 update=SF_UPDATE_PLAIN):
+                 update=SF_UPDATE_PLAIN, eta=None):
         self.rows, self.cols, self.levels = rows, cols, levels
         self.storage = storage
         self.cfg = make_config(rows, cols, levels, max_flow_px, smooth_iters, alpha, storage,
                                update, read_flags)
         self.ctx = sf_create(self.cfg, stream)
-        sf_set_camera(self.ctx, fx, fy, cx, cy)
+        sf_set_camera(self.ctx, fx, fy, cx, cy, eta)
 
-    def push(self, Y, rho, dt):
-        sf_push_frame(self.ctx, Y, rho, dt)
+    def push(self, Y, rho, dt, omega=None, acc=None, omega_dot=None):
+        if omega is None and acc is None and omega_dot is None:
+            sf_push_frame(self.ctx, Y, rho, dt)
+        else:
+            sf_push_frame_ex(self.ctx, Y, rho, dt, omega, omega_dot, acc)
 
     def flow(self, kind=SF_FLOW_W_FRAME, out=None):
         import torch
@@ -525,10 +583,14 @@ class Batch:
                             sp.get("alpha", DEFAULT_ALPHA), storage, update,
                             sp.get("read_flags", 0)) for sp in self.specs]
         self.ctx = sf_create_batch(cfgs, stream)
-        sf_set_cameras(self.ctx, [sp["camera"] for sp in self.specs])
+        sf_set_cameras(self.ctx, [tuple(sp["camera"]) + ((sp["eta"],) if sp.get("eta") is not None
+                                                         else ()) for sp in self.specs])
 
-    def push(self, Ys, rhos, dts):
-        sf_push_frames(self.ctx, Ys, rhos, dts)
+    def push(self, Ys, rhos, dts, omegas=None, accs=None, omega_dots=None):
+        if omegas is None and accs is None and omega_dots is None:
+            sf_push_frames(self.ctx, Ys, rhos, dts)
+        else:
+            sf_push_frames_ex(self.ctx, Ys, rhos, dts, omegas, omega_dots, accs)
 
     def flow(self, stream, kind=SF_FLOW_W_FRAME, out=None):
         import torch
