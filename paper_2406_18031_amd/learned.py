@@ -10,6 +10,7 @@ recurrence stay the plain ones.
 """
 from __future__ import annotations
 
+import os
 from typing import Iterable, List, Sequence, Tuple
 
 import numpy as np
@@ -18,6 +19,20 @@ from . import sflow
 
 CHANNELS = (9, 16, 16, 16, 3)
 N_PARAMS = sflow.SF_LEARNED_PARAMS
+# parameters and fallback threshold trained for the 512x512 three-level box workload
+# (python -m paper_2406_18031_amd.train --out <this file>; seeds and command in the design notes)
+TRAINED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                       "learned_boxes512.npz")
+
+
+def load_trained(path: str = TRAINED):
+    """(parameters float32[N_PARAMS], threshold) from a file written by train.py."""
+    with np.load(path, allow_pickle=False) as z:
+        p = np.asarray(z["params"], dtype=np.float32)
+        t = float(z["threshold"])
+    if p.shape != (N_PARAMS,) or not np.all(np.isfinite(p)):
+        raise ValueError(f"{path}: expected {N_PARAMS} finite parameters")
+    return p, t
 
 
 def layer_slices():
