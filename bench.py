@@ -21,6 +21,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "frames/s at 512x512 (Hz) + HBM GB/s % peak; batched & learned vs plain at EPE"
+# The paper's own runtime tables (GTX-780; mapping onto the Spherepix grid plus the filter,
+# transfers excluded; Hz is a mean of per-frame rates): context for the sweep, not a target.
+PAPER_TABLES = {
+    "runtime_pyramid_1": {"512^2, 1 level, smoothing 2": {"1": 1133.9, "2": 998.1, "4": 755.6}},
+    "runtime_pyramid_2": {"512^2, 2 levels, smoothing [2, 4]": {"1": 747.4, "2": 720.5,
+                                                                 "4": 674.3, "8": 594.7}},
+    "runtime_pyramid_2_1024": {"1024^2, 2 levels, smoothing [2, 4]": {"1": 213.889,
+                                                                      "2": 207.480,
+                                                                      "4": 194.258,
+                                                                      "8": 172.149}},
+}
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3          # published MI355X vector FP32 (packed FMA)
 FP32_UNPACKED_TFLOPS = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
@@ -110,6 +121,7 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
         step(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    graph = graph_pass(f.ctx, step, steps, warmup)
 
     # kernel durations from HIP events on the context stream, over a second pass of the
     # same frames (events add host work, so the throughput pass above runs without them)
@@ -122,7 +134,7 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
     final = f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
     f.close()
     return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n, final=final,
-                tuned=setting)
+                tuned=setting, graph=graph)
 
 
 def run_batched(n_streams, steps, warmup, storage=0, frames=6):
@@ -178,6 +190,7 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
         step(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    graph = graph_pass(b.ctx, step, steps, warmup)
     sflow.sf_set_timing(b.ctx, True)
     sflow.sf_kernel_times(b.ctx, reset=True)
     for k in range(warmup, warmup + steps):
@@ -206,35 +219,147 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
         "level_step_tflops": step_flops / step_s / 1e12,
         "level_step_hbm_gbs": step_bytes / step_s / 1e9,
         "tuned": {"pass_steps": setting["pass_steps"], "tiles": setting["tiles"]},
+        "frame_graph": graph,
     }
 
 
-def run_learned(n_streams, steps, warmup, frames=6):
-    """The learned update on n_streams 512 x 512 box sequences (3 levels, max flow 8 px),
-    plain and learned side by side on the same frames.  The network's parameters are a fresh
-    initialisation: this measures throughput only (the accuracy of trained parameters is a
-    test's business)."""
+def graph_pass(ctx, step, steps, warmup):
+    """The same loop with the frame's launches replayed from a HIP graph (sf_set_graph):
+    throughput, and the host time per step with and without the graph (the loop's wall time
+    up to its last submission, before waiting for the device)."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    out = {}
+    for on in (False, True):
+        sflow.sf_set_graph(ctx, on)
+        for k in range(warmup):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warmup, warmup + steps):
+            step(k)
+        t1 = time.perf_counter()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        key = "graph" if on else "eager"
+        out[f"host_us_per_step_{key}"] = (t1 - t0) / steps * 1e6
+        out[f"steps_per_s_{key}"] = steps / (t2 - t0)
+    sflow.sf_set_graph(ctx, False)
+    return out
+
+
+def run_inertial(steps, warmup):
+    """The prediction with the inertial source terms (sf_push_frame_ex) on the boxes512
+    workload, fed the rates the camera's inertial unit would report (synth: angular velocity and
+    its rate of change at mid-interval, zero inertial acceleration).  Throughput as the headline's loop; accuracy:
+    endpoint error against the true flow over frames 10-99, plain and inertial, on boxes512
+    (20 % of the image motion from rotation) and on a rotation-dominated variant (80 %)."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    from synth.scenes import box_sequence
+    from synth.workloads import workload
+
+    wl = workload("boxes512")
+    out = {}
+    for name, seq in (("boxes512", wl["build"]("cuda")),
+                      ("boxes512_rotation80", box_sequence(512, 512, 100, seed=2, max_flow_px=8.0,
+                                                           rot_share=0.8, device="cuda"))):
+        cam = seq.camera
+        fr = [seq.frame(k, "cuda") for k in range(seq.n_frames)]
+        Ys = [f.Y.to(torch.float32).contiguous() for f in fr]
+        Rs = [f.rho.to(torch.float32).contiguous() for f in fr]
+        Ws = [(f.w_gt * seq.dt).permute(2, 0, 1).to(torch.float32).contiguous() for f in fr]
+        imu = [seq.imu(k) for k in range(seq.n_frames)]
+        del fr
+        dmu = _pinhole_dmu_t(seq, "cuda")
+        F = len(Ys)
+        row = {}
+        for use in (False, True):
+            f = sflow.Filter(seq.rows, seq.cols, wl["levels"], wl["max_flow_px"], wl["smooth"],
+                             cam.fx, cam.fy, cam.cx, cam.cy)
+            err = []
+            for k in range(F):
+                if use:
+                    f.push(Ys[k], Rs[k], seq.dt, omega=imu[k][0], omega_dot=imu[k][1],
+                           acc=imu[k][2])
+                else:
+                    f.push(Ys[k], Rs[k], seq.dt)
+                if k >= 10:
+                    err.append(float(((f.flow(sflow.SF_FLOW_W_FRAME) - Ws[k]).norm(dim=0)
+                                      / dmu).mean()))
+            key = "inertial" if use else "plain"
+            row[f"gt_epe_px_{key}"] = sum(err) / len(err)
+            if use and name == "boxes512":
+                out_t = torch.empty((3, seq.rows, seq.cols), dtype=torch.float32, device="cuda")
+
+                def step(k):
+                    m = imu[k % F]
+                    f.push(Ys[k % F], Rs[k % F], seq.dt, omega=m[0], omega_dot=m[1], acc=m[2])
+                    sflow.sf_get_flow(f.ctx, sflow.SF_FLOW_W_RAD_S, out_t)
+
+                for k in range(warmup):
+                    step(k)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for k in range(warmup, warmup + steps):
+                    step(k)
+                torch.cuda.synchronize()
+                out["frames_per_s"] = steps / (time.perf_counter() - t0)
+            f.close()
+        row["gt_epe_inertial_over_plain"] = row["gt_epe_px_inertial"] / row["gt_epe_px_plain"]
+        out[name] = row
+    out["workload"] = ("boxes512 (and its rotation-dominated variant) with the renderer's "
+                       "angular velocity at mid-interval; accuracy over frames 10-99")
+    return out
+
+
+def _pinhole_dmu_t(seq, device):
+    """Tangent-plane pixel spacing of the finest pinhole grid (closed form), torch float32."""
+    import torch
+    c = seq.camera
+    j = torch.arange(seq.cols, dtype=torch.float64, device=device)[None, :]
+    i = torch.arange(seq.rows, dtype=torch.float64, device=device)[:, None]
+    x = (j - c.cx) / c.fx
+    y = (i - c.cy) / c.fy
+    xn = x + torch.where(j < seq.cols - 1, 1.0, -1.0) / c.fx
+    d = torch.sqrt(1 + y * y) / torch.sqrt(x * x + y * y + 1) / (c.fx * torch.sqrt(xn * xn + y * y + 1))
+    return d.to(torch.float32)
+
+
+def run_learned(n_streams, steps, warmup, frames=6, eval_frames=100, warm=10):
+    """The learned update on n_streams 512 x 512 box sequences (3 levels, max flow 8 px;
+    held-out seeds 20000 + i, not trained on), with the committed trained parameters and the
+    fallback threshold chosen on validation seeds.  Throughput: plain and learned side by side
+    on the same frames (every stream's output read each frame).  Accuracy: endpoint error
+    against the true flow (px/frame) over frames warm..eval_frames-1, plain and learned on the
+    same frames, and the learned form's fallback rate."""
     import torch
     from paper_2406_18031_amd import learned, sflow
     from synth.scenes import box_sequence
 
-    specs, Ys, Rs = [], [], []
+    params, threshold = learned.load_trained()
+    seqs, specs, Ys, Rs = [], [], [], []
     for i in range(n_streams):
-        seq = box_sequence(512, 512, frames, seed=20000 + i, dt=1.0 / 300.0, max_flow_px=8.0,
-                           device="cuda")
+        seq = box_sequence(512, 512, eval_frames, seed=20000 + i, dt=1.0 / 300.0,
+                           max_flow_px=8.0, device="cuda")
         c = seq.camera
+        seqs.append(seq)
         specs.append(dict(rows=512, cols=512, levels=3, max_flow_px=8.0, smooth=[2, 4, 4],
                           camera=(c.fx, c.fy, c.cx, c.cy)))
-        y, r = render_frames(seq, "cuda")
+        y, r = [], []
+        for k in range(frames):
+            f = seq.frame(k, "cuda")
+            y.append(f.Y.to(torch.float32).contiguous())
+            r.append(f.rho.to(torch.float32).contiguous())
         Ys.append(y)
         Rs.append(r)
-        dt = seq.dt
+    dt = seqs[0].dt
+    dts = [dt] * n_streams
     out = {}
     for name, upd in (("plain", sflow.SF_UPDATE_PLAIN), ("learned", sflow.SF_UPDATE_LEARNED)):
         b = sflow.Batch(specs, update=upd)
         if upd == sflow.SF_UPDATE_LEARNED:
-            b.set_learned(learned.init_params(0), 1.0)
-        dts = [dt] * n_streams
+            b.set_learned(params, threshold)
         outs = [torch.empty((3, 512, 512), dtype=torch.float32, device="cuda")
                 for _ in range(n_streams)]
 
@@ -246,8 +371,6 @@ def run_learned(n_streams, steps, warmup, frames=6):
         for k in range(warmup):
             step(k)
         torch.cuda.synchronize()
-        if upd == sflow.SF_UPDATE_LEARNED:
-            b.learned_stats(reset=True)
         t0 = time.perf_counter()
         for k in range(warmup, warmup + steps):
             step(k)
@@ -255,13 +378,91 @@ def run_learned(n_streams, steps, warmup, frames=6):
         el = time.perf_counter() - t0
         out[name] = {"aggregate_frames_per_s": n_streams * steps / el,
                      "ms_per_batch_frame": el / steps * 1e3}
-        if upd == sflow.SF_UPDATE_LEARNED:
-            fb, px = b.learned_stats()
-            out[name]["fallback_rate"] = fb / max(1, px)
         b.close()
+    # accuracy against the true flow, both forms on the same rendered frames
+    bp = sflow.Batch(specs)
+    bl = sflow.Batch(specs, update=sflow.SF_UPDATE_LEARNED)
+    bl.set_learned(params, threshold)
+    dmu = [_pinhole_dmu_t(s, "cuda") for s in seqs]
+    err = {"plain": [], "learned": []}
+    for k in range(eval_frames):
+        fr = [s.frame(k, "cuda") for s in seqs]
+        ys = [f.Y.to(torch.float32).contiguous() for f in fr]
+        rs = [f.rho.to(torch.float32).contiguous() for f in fr]
+        if k == warm:
+            bl.learned_stats(reset=True)
+        for name, b in (("plain", bp), ("learned", bl)):
+            b.push(ys, rs, dts)
+            if k >= warm:
+                e = torch.stack([((b.flow(i, sflow.SF_FLOW_W_FRAME)
+                                   - (f.w_gt * s.dt).permute(2, 0, 1).to(torch.float32))
+                                  .norm(dim=0) / dmu[i]).mean()
+                                 for i, (f, s) in enumerate(zip(fr, seqs))])
+                err[name].append(float(e.mean()))
+    fb, px = bl.learned_stats()
+    bp.close()
+    bl.close()
+    out["plain"]["gt_epe_px"] = float(sum(err["plain"]) / len(err["plain"]))
+    out["learned"]["gt_epe_px"] = float(sum(err["learned"]) / len(err["learned"]))
+    out["learned"]["fallback_rate"] = fb / max(1, px)
+    out["learned"]["threshold"] = threshold
+    out["gt_epe_learned_over_plain"] = out["learned"]["gt_epe_px"] / out["plain"]["gt_epe_px"]
     out["streams"] = n_streams
-    out["workload"] = "512x512 box sequences, 3 levels, max flow 8 px, untrained network"
+    out["workload"] = (f"512x512 box sequences, 3 levels, max flow 8 px, held-out seeds "
+                       f"20000-{20000 + n_streams - 1}; trained parameters "
+                       f"(paper_2406_18031_amd/weights/learned_boxes512.npz); accuracy over "
+                       f"frames {warm}-{eval_frames - 1}")
     return out
+
+
+def run_sweep(steps, warmup, frames=8):
+    """The paper's runtime tables' shapes (512^2 one level; 512^2 and 1024^2 two levels;
+    maximum flow 1/2/4/8 px; smoothing 2 / [2, 4]) on seeded box scenes: frames/s of the push
+    plus output read, and the level step's HIP-event duration per frame."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    from synth.workloads import PAPER_SWEEP, sweep_sequence
+
+    rows = []
+    for t in PAPER_SWEEP:
+        for mf in t["flows"]:
+            seq = sweep_sequence(t["size"], mf, frames, "cuda")
+            Ys, Rs = render_frames(seq, "cuda")
+            c = seq.camera
+            f = sflow.Filter(t["size"], t["size"], t["levels"], mf, t["smooth"], c.fx, c.fy,
+                             c.cx, c.cy)
+            out = torch.empty((3, t["size"], t["size"]), dtype=torch.float32, device="cuda")
+
+            def step(k):
+                f.push(Ys[k % frames], Rs[k % frames], seq.dt)
+                sflow.sf_get_flow(f.ctx, sflow.SF_FLOW_W_RAD_S, out)
+
+            for k in range(warmup):
+                step(k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(warmup, warmup + steps):
+                step(k)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            sflow.sf_set_timing(f.ctx, True)
+            sflow.sf_kernel_times(f.ctx, reset=True)
+            for k in range(warmup, warmup + steps):
+                step(k)
+            ms, n = sflow.sf_kernel_times(f.ctx, reset=True)
+            f.close()
+            levels = level_table(t["size"], t["size"], t["levels"], mf, t["smooth"])
+            rows.append({
+                "table": t["table"], "size": t["size"], "levels": t["levels"],
+                "smooth": t["smooth"], "max_flow_px": mf,
+                "N": [L["N"] for L in levels],
+                "frames_per_s": steps / el, "ms_per_frame": el / steps * 1e3,
+                "mpix_per_s": t["size"] ** 2 * steps / el / 2 ** 20,
+                "level_step_us_per_frame": ms[1] / steps * 1e3,
+            })
+            print(f"[sweep] {t['table']} {t['size']}^2 H={t['levels']} flow {mf:g}: "
+                  f"{rows[-1]['frames_per_s']:.0f} frames/s", flush=True)
+    return rows
 
 
 def cpu_baseline(wl_name, budget_s=20.0):
@@ -311,6 +512,25 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_step_boxes512_counters.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2406_18031_amd", "csrc", "sflow_kernels.hip")
 
 
+TRACE = os.path.join(ROOT, "profiles", "k_step_boxes512_trace.md")
+
+
+def traced_kernel_us():
+    """Average duration (us) of the level-step kernel in the committed rocprofv3 kernel trace of
+    the boxes512 workload, or None when the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(TRACE):
+        return None
+    txt = open(TRACE).read()
+    with open(KERNEL_SOURCE, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if sha not in txt:
+        return None
+    m = re.search(r"^\| k_step<float[^|]*\| *\d+ *\| *(\d+) *\|", txt, re.M)
+    return float(m.group(1)) * 1e-3 if m else None
+
+
 def measured_counters():
     """Values per level-step launch from the committed rocprofv3 counter summary: HBM bytes
     (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy of known size) and
@@ -334,23 +554,33 @@ def measured_counters():
             if "valu_instructions_per_launch" in vals else None}
 
 
-def copy_probe(mib: int, reps: int = 20):
-    """A plain device copy of known size, for scaling the HBM byte counters."""
+def copy_probe(mib: int, reps: int = 10, quiet: bool = False):
+    """The library's plain streaming copy (sf_copy_probe) of `mib` MiB, timed with HIP events
+    on its stream: the achievable HBM bandwidth (bytes read + written per second), and a
+    copy of known size for scaling the HBM byte counters."""
     import torch
-    n = mib * 2 ** 20 // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    from paper_2406_18031_amd import sflow
+    n = mib * 2 ** 20
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    # an elementwise kernel (not the runtime's DMA path): reads and writes n floats once
-    for _ in range(3):
-        torch.mul(a, 1.0, out=b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    s = torch.cuda.current_stream()
+    for _ in range(2):
+        sflow.sf_copy_probe(a, b, n, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
     for _ in range(reps):
-        torch.mul(a, 1.0, out=b)
+        sflow.sf_copy_probe(a, b, n, s.cuda_stream)
+    e1.record(s)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
-                      "launches": reps + 3, "gbs": 2 * n * 4 * reps / el / 1e9}), flush=True)
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(a[:1024], b[:1024]) and torch.equal(a[-1024:], b[-1024:])
+    res = {"copy_bytes_read": n, "copy_bytes_written": n, "launches": reps + 2,
+           "us_per_copy": ms * 1e3, "gbs": 2 * n / (ms * 1e-3) / 1e9}
+    del a, b
+    torch.cuda.empty_cache()
+    if not quiet:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -364,6 +594,9 @@ def main():
     ap.add_argument("--streams", type=int, default=64)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the paper's runtime-table shapes and print them as one "
+                         "JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the filter runs on a single device and this build "
@@ -371,6 +604,10 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.sweep:
+        rows = run_sweep(args.steps, args.warmup)
+        print(json.dumps({"sweep": rows, "paper": PAPER_TABLES}), flush=True)
         return
 
     r = run_gpu(args.workload, args.steps, args.warmup, storage=0)
@@ -384,6 +621,8 @@ def main():
     counters = measured_counters() if args.workload == "boxes512" else None
     achieved_tflops = step_flops / (step_ms * 1e-3) / 1e12
     achieved_gbs = step_bytes / (step_ms * 1e-3) / 1e9
+    traced = traced_kernel_us() if args.workload == "boxes512" else None
+    copy = copy_probe(4096, quiet=True)      # 4 GiB: far beyond the 256 MB last-level cache
 
     print(f"[bench] {args.workload}: {fps:.1f} frames/s, level-step kernel {step_ms * 1e3:.2f} us"
           f" ({achieved_gbs:.0f} GB/s algorithmic, {achieved_tflops:.2f} TFLOP/s)", flush=True)
@@ -419,8 +658,16 @@ def main():
             "kernel_us": step_ms * 1e3,
             "algorithmic_flops": step_flops,
             "algorithmic_bytes": step_bytes,
+            # the same kernel's average duration in the committed rocprofv3 kernel trace of this
+            # workload (null when the kernel source changed since), and the fraction it gives
+            "kernel_us_rocprof": traced,
+            "frac_rocprof": (step_flops / (traced * 1e-6) / 1e12 / FP32_PEAK_TFLOPS
+                             if traced else None),
             "hbm_achieved_gbs": achieved_gbs,
             "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
+            # a plain streaming copy of 4 GiB (sf_copy_probe), the bandwidth reachable in practice
+            "hbm_copy_gbs": copy["gbs"],
+            "hbm_frac_of_copy": achieved_gbs / copy["gbs"],
             "frac_of_unpacked_fp32": achieved_tflops / FP32_UNPACKED_TFLOPS,
             # VALU wave64 instructions retired per SIMD per 4 cycles over the launch
             # (SQ_INSTS_VALU of the committed counters against 256 CUs x 4 SIMDs x 2.4 GHz x
@@ -431,11 +678,15 @@ def main():
             "valu_rate_nominal": (counters["valu"] * 4 / (256 * 4 * 2.4e9 * step_ms * 1e-3)
                                   if counters and counters["valu"] else None),
         },
-        "kernel_us_per_frame": {k: v / max(1, n) * 1e3 * n / args.steps for k, v, n in
-                                zip(("pyramid", "level_step", "reconstruct"), r["kernel_ms"],
-                                    r["kernel_n"])},
+        # HIP events around every launch of a second pass over the same frames: each pair adds
+        # about a microsecond, so for the short pyramid and reconstruction launches these are
+        # upper bounds (their rocprofv3 durations are the figures to use)
+        "kernel_us_per_frame_event_upper_bound": {
+            k: v / max(1, n) * 1e3 * n / args.steps for k, v, n in
+            zip(("pyramid", "level_step", "reconstruct"), r["kernel_ms"], r["kernel_n"])},
         "paper_context": {"hz": 594.7, "workload": "512x512, 2 levels, max flow 8 px, GTX-780",
                           "source": "Table runtime_pyramid_2"},
+        "frame_graph": r["graph"],
     }
     forms = {}
     if not args.no_forms:
@@ -477,10 +728,19 @@ def main():
         }
         print(f"[bench] large 2048x1024 fp16: {forms['large_2048x1024_fp16']['frames_per_s']:.1f} "
               f"frames/s", flush=True)
+        ri = run_inertial(args.steps, args.warmup)
+        forms["inertial_boxes512"] = ri
+        print(f"[bench] inertial terms: {ri['frames_per_s']:.1f} frames/s; true-flow EPE "
+              f"boxes512 {ri['boxes512']['gt_epe_px_inertial']:.4f} px (plain "
+              f"{ri['boxes512']['gt_epe_px_plain']:.4f}), 80 % rotation "
+              f"{ri['boxes512_rotation80']['gt_epe_px_inertial']:.4f} px (plain "
+              f"{ri['boxes512_rotation80']['gt_epe_px_plain']:.4f})", flush=True)
         rl = run_learned(16, max(5, args.steps // 5), 2)
         forms["learned_16x512"] = rl
         print(f"[bench] learned 16x512: {rl['learned']['aggregate_frames_per_s']:.1f} "
-              f"stream-frames/s (plain {rl['plain']['aggregate_frames_per_s']:.1f})", flush=True)
+              f"stream-frames/s (plain {rl['plain']['aggregate_frames_per_s']:.1f}); true-flow "
+              f"EPE {rl['learned']['gt_epe_px']:.4f} px (plain {rl['plain']['gt_epe_px']:.4f}), "
+              f"fallback rate {rl['learned']['fallback_rate']:.3f}", flush=True)
         res["forms"] = forms
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.workload)

@@ -42,6 +42,24 @@ def workload(name: str):
     return WORKLOADS[name]
 
 
+# The shapes of the paper's runtime tables (Section "Experimental Validation", Tables
+# runtime_pyramid_1, runtime_pyramid_2, runtime_pyramid_2_1024): image size, levels, smoothing
+# passes per level (finest first) and the maximum flows the rows are quoted at.  Seeded box
+# scenes at 300 Hz (1024 x 1024 at the ZED's 1024-wide resolution) stand in for the paper's
+# rendered city and stereo recordings; the motion is scaled to each row's maximum flow.
+PAPER_SWEEP = (
+    dict(table="runtime_pyramid_1", size=512, levels=1, smooth=[2], flows=(1.0, 2.0, 4.0)),
+    dict(table="runtime_pyramid_2", size=512, levels=2, smooth=[2, 4], flows=(1.0, 2.0, 4.0, 8.0)),
+    dict(table="runtime_pyramid_2_1024", size=1024, levels=2, smooth=[2, 4],
+         flows=(1.0, 2.0, 4.0, 8.0)),
+)
+
+
+def sweep_sequence(size: int, max_flow_px: float, n_frames: int, device="cpu"):
+    return box_sequence(size, size, n_frames, seed=5, dt=1.0 / 300.0, max_flow_px=max_flow_px,
+                        device=device)
+
+
 _MIX_SIZES = (256, 512, 1024)
 
 

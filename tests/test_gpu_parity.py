@@ -275,3 +275,20 @@ def test_driving_2048x1024_fp16():
         log(f"    EPE mean {e['mean']:.2e} p99 {e['p99']:.2e} max {e['max']:.2e}")
         check_bar(e, 1, ("2048x1024 crop", k))
     g.close()
+
+
+def test_paper_shape_1024_two_levels():
+    """The shape of the paper's 1024x1024 runtime table (two levels, smoothing [2, 4], the
+    largest flow of 8 px: N = 8/4), on the sweep's seeded box scene at full size: every pixel
+    of every output kind over three frames against the oracle."""
+    import torch
+    from synth.workloads import sweep_sequence
+    seq = sweep_sequence(1024, 8.0, 3, "cuda")
+    c = seq.camera
+    frames = []
+    for k in range(seq.n_frames):
+        f = seq.frame(k, "cuda")
+        frames.append((f.Y.to(torch.float32).cpu().numpy(), f.rho.to(torch.float32).cpu().numpy()))
+    w = _run(frames, 1024, 1024, 2, 8.0, [2, 4], (c.fx, c.fy, c.cx, c.cy),
+             dts=[seq.dt] * seq.n_frames)
+    log("1024x1024 two levels worst mean EPE", w)
