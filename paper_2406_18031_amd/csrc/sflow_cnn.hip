@@ -220,26 +220,45 @@ __global__ void __launch_bounds__(256) k_conv_dw(DwArgs a) {
 }
 
 // loss: Charbonnier endpoint error between the network's output (FP32 planes, 3 channels) and
-// the target; writes d loss / d output as BF16 NHWC (16 channels, 3 used) and adds the loss.
+// the target; writes d loss / d output as BF16 NHWC (16 channels, 3 used; one pixel's 32 bytes
+// in two 16-byte stores) and adds the loss: a wave sum by lane shuffles, a block sum through
+// LDS, one atomic add per block.
 __global__ void __launch_bounds__(256) k_loss(LossArgs a) {
+    __shared__ float wsum[256 / 64];
     const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.segs.total) return;
-    const int sgi = find_seg(a.segs, p);
-    const int i = p - a.segs.base[sgi];
-    const bool valid = i < a.segs.rows[sgi] * a.segs.cols[sgi];
+    const bool in = p < a.segs.total;
     float d[3] = {0, 0, 0};
-    float n = 1.0f;
-    if (valid) {
-        float s2 = a.eps * a.eps;
-        for (int c = 0; c < 3; ++c) {
-            d[c] = a.out[(size_t)c * a.segs.total + p] - a.target[(size_t)c * a.segs.total + p];
-            s2 = fmaf(d[c], d[c], s2);
+    float n = 1.0f, l = 0.0f;
+    bool valid = false;
+    if (in) {
+        const int sgi = find_seg(a.segs, p);
+        const int i = p - a.segs.base[sgi];
+        valid = i < a.segs.rows[sgi] * a.segs.cols[sgi];
+        if (valid) {
+            float s2 = a.eps * a.eps;
+            for (int c = 0; c < 3; ++c) {
+                d[c] = a.out[(size_t)c * a.segs.total + p] - a.target[(size_t)c * a.segs.total + p];
+                s2 = fmaf(d[c], d[c], s2);
+            }
+            n = sqrtf(s2);
+            l = n * a.inv_count;
         }
-        n = sqrtf(s2);
-        atomicAdd(a.loss, n * a.inv_count);
+        uint32_t g[3];
+        for (int c = 0; c < 3; ++c) g[c] = valid ? f2bf(d[c] / n * a.inv_count) : 0u;
+        uint4* o = reinterpret_cast<uint4*>(a.dout + (size_t)p * 16);
+        o[0] = make_uint4(g[0] | (g[1] << 16), g[2], 0u, 0u);
+        o[1] = make_uint4(0u, 0u, 0u, 0u);
     }
-    for (int c = 0; c < 16; ++c)
-        a.dout[(size_t)p * 16 + c] = (valid && c < 3) ? f2bf(d[c] / n * a.inv_count) : (uint16_t)0;
+    // every lane of the block takes part in the sums (lanes past the end add 0)
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wsum[wave] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < 256 / 64; ++w) t += wsum[w];
+        atomicAdd(a.loss, t);
+    }
 }
 
 // FP32 planar inputs (C planes of `total` pixels) -> BF16 NHWC 16 channels
