@@ -339,6 +339,16 @@ class Sequence:
             rho = rho_true * (1.0 + self.depth_noise * z)
         return Frame(Y=Y, rho=rho, w_gt=w, rho_true=rho_true)
 
+    def right_image(self, k: int, baseline: float, device="cpu") -> "torch.Tensor":
+        """Brightness seen at frame k by the right camera of a rectified stereo pair: the same
+        orientation and rays, its centre `baseline` metres along the left camera's x axis."""
+        R, p = self.Rs[k], self.ps[k]
+        eta = self._rays(device)
+        Rt = torch.as_tensor(R, dtype=torch.float64, device=device)
+        d = eta @ Rt.T
+        _, Y = self.scene.cast(p + R @ np.array([baseline, 0.0, 0.0]), d)
+        return Y
+
     def imu(self, k: int):
         """What an inertial measurement unit on the camera reports for the interval from frame
         k - 1 to frame k, as the filter takes it (constant over the interval): the body-frame
