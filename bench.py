@@ -122,6 +122,7 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     graph = graph_pass(f.ctx, step, steps, warmup)
+    overlap = overlap_pass(f.ctx, step, steps, warmup)
 
     # kernel durations from HIP events on the context stream, over a second pass of the
     # same frames (events add host work, so the throughput pass above runs without them)
@@ -134,7 +135,7 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
     final = f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
     f.close()
     return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n, final=final,
-                tuned=setting, graph=graph)
+                tuned=setting, graph=graph, overlap=overlap)
 
 
 def run_batched(n_streams, steps, warmup, storage=0, frames=6):
@@ -221,6 +222,28 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=6):
         "tuned": {"pass_steps": setting["pass_steps"], "tiles": setting["tiles"]},
         "frame_graph": graph,
     }
+
+
+def overlap_pass(ctx, step, steps, warmup):
+    """The same loop with the frames declared as produced on a stream of their own
+    (sf_set_input_stream; they are resident in HBM already, so that stream holds no work): each
+    frame's pyramid then runs on the library's pyramid stream beside the previous frame's level
+    step.  Throughput over the same frames, and the final flow for a bitwise check against the
+    default mode."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    s_in = torch.cuda.Stream()
+    sflow.sf_set_input_stream(ctx, s_in)
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        step(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sflow.sf_set_input_stream(ctx, None)
+    return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3}
 
 
 def graph_pass(ctx, step, steps, warmup):
@@ -310,6 +333,95 @@ def run_inertial(steps, warmup):
         out[name] = row
     out["workload"] = ("boxes512 (and its rotation-dominated variant) with the renderer's "
                        "angular velocity at mid-interval; accuracy over frames 10-99")
+    return out
+
+
+def run_grid_stereo(steps, warmup, frames=40, warm=10):
+    """Two forms beyond the pinhole depth-sensor filter, on 512x512 box scenes (3 levels,
+    max flow 8 px):
+    - grid: a 90-degree equiangular grid of 512x512 directions fed by a 640x640 pinhole camera;
+      each step maps the camera's frame onto the grid (sf_map_frame) and pushes it;
+    - stereo: the inverse depth taken from a rectified stereo pair (baseline 0.1 m) each frame
+      (sf_stereo_depth) instead of a depth sensor; throughput, and the true-flow endpoint
+      error over frames warm..frames-1 against the same filter fed the scene's depth (1 %
+      noise)."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    from synth.scenes import box_sequence, equiangular_rays
+    out = {}
+    # grid + mapping
+    src = box_sequence(640, 640, 8, seed=2, max_flow_px=10.0, device="cuda")
+    c = src.camera
+    Ys, Rs = render_frames(src, "cuda")
+    eta = equiangular_rays(512, 512, 90.0)
+    g = sflow.Filter(512, 512, 3, 8.0, [2, 4, 4], 256.0, 256.0, 255.5, 255.5, eta=eta)
+    g.set_source_camera(c.fx, c.fy, c.cx, c.cy, 640, 640)
+    Yg = torch.empty((512, 512), dtype=torch.float32, device="cuda")
+    Rg = torch.empty_like(Yg)
+    o = torch.empty((3, 512, 512), dtype=torch.float32, device="cuda")
+
+    def gstep(k):
+        g.map(Ys[k % 8], Rs[k % 8], Yg, Rg)
+        g.push(Yg, Rg, src.dt)
+        sflow.sf_get_flow(g.ctx, sflow.SF_FLOW_W_RAD_S, o)
+
+    for k in range(warmup):
+        gstep(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        gstep(k)
+    torch.cuda.synchronize()
+    out["grid_equiangular_512"] = {
+        "frames_per_s": steps / (time.perf_counter() - t0),
+        "workload": "512x512 equiangular grid of 90 degrees, frames mapped from a 640x640 "
+                    "pinhole camera each step (map + push + read)"}
+    g.close()
+    # stereo
+    b = 0.1
+    seq = box_sequence(512, 512, frames, seed=2, max_flow_px=8.0, device="cuda")
+    c = seq.camera
+    fr = [seq.frame(k, "cuda") for k in range(frames)]
+    YL = [f.Y.to(torch.float32).contiguous() for f in fr]
+    YR = [seq.right_image(k, b, "cuda").to(torch.float32).contiguous() for k in range(frames)]
+    RD = [f.rho.to(torch.float32).contiguous() for f in fr]
+    W = [(f.w_gt * seq.dt).permute(2, 0, 1).to(torch.float32).contiguous() for f in fr]
+    del fr
+    dmu = _pinhole_dmu_t(seq, "cuda")
+    cam = (c.fx, c.fy, c.cx, c.cy)
+    dmax = 16
+    row = {}
+    for mode in ("stereo", "depth"):
+        f = sflow.Filter(512, 512, 3, 8.0, [2, 4, 4], *cam)
+        f.set_stereo(b, dmax)
+        rho = torch.empty((512, 512), dtype=torch.float32, device="cuda")
+        err = []
+        for k in range(frames):
+            if mode == "stereo":
+                f.stereo_depth(YL[k], YR[k], rho)
+                f.push(YL[k], rho, seq.dt)
+            else:
+                f.push(YL[k], RD[k], seq.dt)
+            if k >= warm:
+                err.append(float(((f.flow(sflow.SF_FLOW_W_FRAME) - W[k]).norm(dim=0) / dmu).mean()))
+        row[f"gt_epe_px_{mode}"] = sum(err) / len(err)
+        if mode == "stereo":
+            def sstep(k):
+                f.stereo_depth(YL[k % frames], YR[k % frames], rho)
+                f.push(YL[k % frames], rho, seq.dt)
+                sflow.sf_get_flow(f.ctx, sflow.SF_FLOW_W_RAD_S, o)
+            for k in range(warmup):
+                sstep(k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(warmup, warmup + steps):
+                sstep(k)
+            torch.cuda.synchronize()
+            row["frames_per_s"] = steps / (time.perf_counter() - t0)
+        f.close()
+    row["workload"] = (f"boxes512 scene seen by a rectified stereo pair (baseline {b} m, "
+                       f"disparities up to {dmax} px); accuracy over frames {warm}-{frames - 1}")
+    out["stereo_boxes512"] = row
     return out
 
 
@@ -687,7 +799,12 @@ def main():
         "paper_context": {"hz": 594.7, "workload": "512x512, 2 levels, max flow 8 px, GTX-780",
                           "source": "Table runtime_pyramid_2"},
         "frame_graph": r["graph"],
+        # the same frames declared as produced on a stream of their own (sf_set_input_stream):
+        # the pyramid runs beside the previous frame's level step
+        "input_stream": r["overlap"],
     }
+    print(f"[bench] {args.workload} with an input stream: "
+          f"{r['overlap']['steps_per_s']:.1f} frames/s", flush=True)
     forms = {}
     if not args.no_forms:
         import numpy as np
@@ -735,6 +852,13 @@ def main():
               f"{ri['boxes512']['gt_epe_px_plain']:.4f}), 80 % rotation "
               f"{ri['boxes512_rotation80']['gt_epe_px_inertial']:.4f} px (plain "
               f"{ri['boxes512_rotation80']['gt_epe_px_plain']:.4f})", flush=True)
+        rg = run_grid_stereo(args.steps, args.warmup)
+        forms.update(rg)
+        st = rg["stereo_boxes512"]
+        print(f"[bench] grid 512x512 with mapping: "
+              f"{rg['grid_equiangular_512']['frames_per_s']:.1f} frames/s; stereo: "
+              f"{st['frames_per_s']:.1f} frames/s, true-flow EPE {st['gt_epe_px_stereo']:.4f} px "
+              f"(depth sensor {st['gt_epe_px_depth']:.4f})", flush=True)
         rl = run_learned(16, max(5, args.steps // 5), 2)
         forms["learned_16x512"] = rl
         print(f"[bench] learned 16x512: {rl['learned']['aggregate_frames_per_s']:.1f} "

@@ -237,6 +237,48 @@ sf_status sf_set_tile(sf_ctx ctx, int32_t level, int32_t tw, int32_t th);
  * SF_ERR_UNSUPPORTED if some level's last pass would not fit. */
 sf_status sf_set_pass_steps(sf_ctx ctx, int32_t steps);
 
+/* ---- mapping a camera's frame onto a stream's grid ----------------------------------------
+ * The paper maps each camera image and depth map onto its spherical grid before the filter runs
+ * (Section "Experimental Validation"; Section "Spherical image data structure").  After
+ * sf_set_source_camera names the pinhole camera (intrinsics, size; eta must be NULL) that
+ * produces a stream's frames, sf_map_frame resamples one frame of that camera onto the stream's
+ * finest grid (its camera's eta, or its pinhole grid): grid direction eta looks at source pixel
+ * (u, v) = (fx eta_x / eta_z + cx, fy eta_y / eta_z + cy); brightness is interpolated bilinearly
+ * with the source clamped to its edge; inverse depth (1/m, NaN = missing) bilinearly over the
+ * valid neighbours, missing where they carry less than half of the weight or where the
+ * direction is more than 1e-3 px outside the image or behind the camera.  Y_src, rho_src are
+ * device images of the source size, Y_out, rho_out device images of the stream's finest size,
+ * all in the context's storage type; enqueued on the context stream.  The outputs are what
+ * sf_push_frame takes. */
+sf_status sf_set_source_camera(sf_ctx ctx, int32_t stream, const sf_camera* src, int32_t rows,
+                               int32_t cols);
+sf_status sf_map_frame(sf_ctx ctx, int32_t stream, const void* Y_src, const void* rho_src,
+                       void* Y_out, void* rho_out);
+
+/* ---- inverse depth from a rectified stereo pair ----------------------------------------------
+ * The paper's proposed extension (Section "Conclusions and Future Work"): take the depth
+ * measurements from the disparity of a coupled stereo pair, so that the filter runs on image
+ * data alone.  The left camera is the stream's pinhole camera (a stream with an eta grid is
+ * SF_ERR_UNSUPPORTED); the right camera has the same intrinsics and orientation, its centre
+ * `baseline` metres along the left camera's x axis (rectified pair).  A point at inverse range
+ * rho along the left direction eta appears kappa rho pixels to the left on the same row,
+ * kappa = fx baseline sqrt(x^2 + y^2 + 1), x = (j - cx)/fx, y = (i - cy)/fy.
+ * sf_stereo_depth writes, per pixel of the finest level: the integer disparity in
+ * [0, max_disparity] minimising the sum of absolute differences over a 5x5 window (rows and
+ * columns clamped to the image; float32 sums over window rows then columns; the smallest on
+ * ties), refined by `iterations` Gauss-Newton steps on the window's squared residuals with the
+ * right image interpolated linearly along the row (kept in [0, max_disparity + 1]), as the
+ * inverse depth d / kappa (1/m); NaN (missing) where the window's sum of squared row slopes of
+ * the right image is below `texture`, its mean absolute residual above `residual`, or j - d < 0.
+ * Images are device, rows x cols of the stream, in the context's storage type; enqueued on the
+ * context stream.  The output is what sf_push_frame takes as rho.  Ranges: baseline > 0,
+ * max_disparity in [0, 64], iterations in [0, 16], texture >= 0, residual > 0 (for images in
+ * [0, 1]: 3, 2.5e-3 and 0.05 work well). */
+sf_status sf_set_stereo(sf_ctx ctx, int32_t stream, double baseline, int32_t max_disparity,
+                        int32_t iterations, double texture, double residual);
+sf_status sf_stereo_depth(sf_ctx ctx, int32_t stream, const void* Y_left, const void* Y_right,
+                          void* rho_out);
+
 /* Kernel timing for measurement.  When enabled, every push records HIP events around each
  * kernel on the context stream; sf_kernel_times returns, per kernel kind (0 pyramid,
  * 1 level step, 2 reconstruction), the total milliseconds and launch counts since the
@@ -254,6 +296,23 @@ sf_status sf_kernel_times(sf_ctx ctx, double* ms3, int64_t* launches3, int32_t r
  * length or learned parameters.  Not used while kernel timing is on.  Disabling releases them
  * (synchronises the stream). */
 sf_status sf_set_graph(sf_ctx ctx, int32_t enable);
+
+/* Frame inputs produced on another stream.  sf_set_input_stream names the HIP stream on which
+ * the caller produces (or copies in) the frames it pushes; NULL or the context stream restores
+ * the default, where every launch of a push is ordered after the work already enqueued on the
+ * context stream.  With another stream, a push orders the launches that read the frame's Y and
+ * rho after the work enqueued so far on that stream only, and builds the frame's pyramid on a
+ * stream of the library's own (default priority), so that it runs beside the previous frame's
+ * level step and reconstruction instead of after them; the level step and every later launch
+ * stay on the context stream, which waits for the pyramid.  The pyramid planes alternate
+ * between two buffers from frame to frame, so no frame's pyramid overwrites one still being
+ * read.  A frame's input buffers stay in use until the next push returns: that push makes the
+ * input stream wait until the earlier frame's launches are done with them, so work enqueued on
+ * the input stream afterwards may rewrite them (a caller reusing buffers keeps two sets).
+ * Results are bitwise those of the default mode.  With frame graphs or kernel timing on, the
+ * pyramid stays on the context stream (which then waits for the input stream).  The stream
+ * must stay valid while it is set.  Synchronises the context stream. */
+sf_status sf_set_input_stream(sf_ctx ctx, void* hip_stream);
 
 /* ---- learned update ----------------------------------------------------------------------
  * An extension beyond the paper, which uses the least-squares update of Section "State

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsflow.so")
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sflow_kernels.hip", "sflow_cnn.hip",
                                                          "sflow_abi.hip", "sflow_net.hip",
-                                                         "sflow_copy.hip")]
+                                                         "sflow_copy.hip", "sflow_stereo.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: no packed FP32 instructions in device code; -ffp-contract=off: only the

@@ -34,6 +34,12 @@ struct StreamInfo {
     double cam[4] = {0, 0, 0, 0};
     double dt_prev = 0.0;
     bool update_ran = false;       // an update has run since the camera or the state was set
+    bool stereo = false;           // stereo parameters for sf_stereo_depth are set
+    double baseline = 0.0, texture = 0.0, residual = 0.0;
+    int dmax = 0, iters = 0;
+    bool source = false;           // a source camera for sf_map_frame is set
+    double src[4] = {0, 0, 0, 0};  // its intrinsics
+    int src_rows = 0, src_cols = 0;
 };
 
 struct sf_ctx_s {
@@ -66,6 +72,7 @@ struct sf_ctx_s {
     float* mid = nullptr;           // FP32 fields between passes (two sets per split level)
     float* geo = nullptr;           // geometry tables of every level (general grids), or NULL
     bool grid = false;              // the level steps read geometry tables
+    bool grid_pinhole[kMaxStreams] = {};   // stream s's table holds its pinhole's own rays
     size_t mid_bytes = 0;
     size_t lds_bytes = 0;
     int max_levels = 0;
@@ -108,6 +115,16 @@ struct sf_ctx_s {
     bool graph_on = false;
     hipStream_t cap = nullptr;            // private stream the frame is captured on
     FrameGraph graphs[2][2];              // [parity][inertial]
+    // Inputs produced on a stream of the caller's (sf_set_input_stream): each push builds the
+    // frame's pyramid on pyr_stream, after the work on in_stream (ev_in) and after the level
+    // step that last read the pyramid buffer it writes (ev_step[buffer]); the context stream
+    // waits for the pyramid (ev_pyr); the input stream waits for the previous frame's level
+    // step before the push returns.
+    hipStream_t in_stream = nullptr;      // NULL: inputs are ordered on the context stream
+    hipStream_t pyr_stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_pyr = nullptr, ev_step[2] = {nullptr, nullptr};
+    bool step_rec[2] = {false, false};    // ev_step[m] holds a frame's record
+    int mbuf = 0;                         // pyramid buffer of the next frame
 };
 
 static std::string g_create_error;
@@ -435,7 +452,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
             L.child = h > 0 ? si.e0 + h - 1 : -1;
             L.parent = h + 1 < si.H ? si.e0 + h + 1 : -1;
             L.flags = cf[s].read_flags;
-            const int nplanes = 2 * (3 + (L.top ? 0 : 3) + 2) + (h > 0 ? 2 : 0);
+            const int nplanes = 2 * (3 + (L.top ? 0 : 3) + 2) + (h > 0 ? 4 : 0);
             total += nplanes * plane_bytes(r, L.pitch);
             ctx->lv.push_back(L);
             r = (r + 1) / 2;
@@ -461,8 +478,10 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
             L.rho[par] = take(pb);
             L.Y[par] = take(pb);
         }
-        L.Ym = L.level > 0 ? take(pb) : nullptr;
-        L.Rm = L.level > 0 ? take(pb) : nullptr;
+        for (int m = 0; m < 2; ++m) {
+            L.Ym[m] = L.level > 0 ? take(pb) : nullptr;
+            L.Rm[m] = L.level > 0 ? take(pb) : nullptr;
+        }
     }
     ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * (ctx->lv.size() + kLevelPad));
     if (cf[0].update == SF_UPDATE_LEARNED) {
@@ -765,6 +784,9 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
     }
     c->grid = new_geo != nullptr;
     c->geo = new_geo;
+    bool old_pin[kMaxStreams];
+    memcpy(old_pin, c->grid_pinhole, sizeof old_pin);
+    for (int s = 0; s < c->S; ++s) c->grid_pinhole[s] = cams[s].eta == nullptr;
     sf_status s2 = upload_levels(c);
     if (s2 != SF_OK) {
         if (!c->hip_failed) {   // nothing was uploaded: the context stays as it was
@@ -772,6 +794,7 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
             c->st = old_st;
             c->geo = old_geo;
             c->grid = old_grid;
+            memcpy(c->grid_pinhole, old_pin, sizeof old_pin);
             if (new_geo) (void)hipFree(new_geo);
         }
         return s2;
@@ -907,6 +930,25 @@ sf_status sf_set_graph(sf_ctx c, int32_t enable) {
     if (st != SF_OK) return st;
     if (!enable) drop_graphs(c);
     c->graph_on = enable != 0;
+    return SF_OK;
+}
+
+sf_status sf_set_input_stream(sf_ctx c, void* hip_stream) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (s == c->stream) s = nullptr;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->pyr_stream) HIP_TRY(c, hipStreamSynchronize(c->pyr_stream));
+    if (s && !c->pyr_stream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->pyr_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_pyr, hipEventDisableTiming));
+        for (int m = 0; m < 2; ++m)
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_step[m], hipEventDisableTiming));
+    }
+    c->in_stream = s;
+    c->step_rec[0] = c->step_rec[1] = false;
     return SF_OK;
 }
 
@@ -1069,13 +1111,15 @@ static sf_status enqueue_pyramid(sf_ctx c, const FrameInputs& in, hipStream_t st
     return SF_OK;
 }
 
-// Every launch of a frame after the first on stream strm: the pyramid, the level-step launches
+// Every launch of a frame after the first on stream strm: the pyramid (unless it was enqueued
+// on the pyramid stream), the level-step launches
 // (reading the state of `parity`), the learned update, and the reconstruction of all but the
 // finest pair of levels (that one waits: recon_pending).
 static sf_status enqueue_frame(sf_ctx c, const FrameInputs& in, bool inertial,
                                const Inertial* imu, int parity, hipStream_t strm,
-                               std::vector<sf_ctx_s::FrameArgsNode>* rec) {
-    sf_status st = enqueue_pyramid(c, in, strm, rec);
+                               std::vector<sf_ctx_s::FrameArgsNode>* rec,
+                               bool with_pyramid = true) {
+    sf_status st = with_pyramid ? enqueue_pyramid(c, in, strm, rec) : SF_OK;
     if (st != SF_OK) return st;
     for (const auto& sl : c->step_launches) {
         StepArgs a{};
@@ -1246,6 +1290,23 @@ static sf_status push_frames(sf_ctx c, const void* const* Y, const void* const* 
         const double dp = c->st[s].dt_prev;
         in.scale[s] = (c->frames == 0 || dt[s] == dp) ? 1.0f : (float)(dt[s] / dp);
     }
+    in.mbuf = c->mbuf;
+    // inputs on the caller's input stream: the pyramid on the library's pyramid stream (frames
+    // after the first, eager launches without timing marks), else everything on the context
+    // stream after the input stream's work
+    const bool ovl = c->in_stream != nullptr;
+    const bool side = ovl && c->frames > 0 && !c->timing && !c->graph_on;
+    if (ovl) HIP_TRY(c, hipEventRecord(c->ev_in, c->in_stream));
+    if (ovl && !side) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    if (side) {
+        HIP_TRY(c, hipStreamWaitEvent(c->pyr_stream, c->ev_in, 0));
+        if (c->step_rec[c->mbuf])
+            HIP_TRY(c, hipStreamWaitEvent(c->pyr_stream, c->ev_step[c->mbuf], 0));
+        st = enqueue_pyramid(c, in, c->pyr_stream, nullptr);
+        if (st != SF_OK) return st;
+        HIP_TRY(c, hipEventRecord(c->ev_pyr, c->pyr_stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_pyr, 0));
+    }
     if (c->frames == 0) {
         st = enqueue_pyramid(c, in, c->stream, nullptr);
         if (st != SF_OK) return st;
@@ -1278,7 +1339,7 @@ static sf_status push_frames(sf_ctx c, const void* const* Y, const void* const* 
         if (c->graph_on && !c->timing)
             st = replay_frame(c, in, inertial, imu);
         else
-            st = enqueue_frame(c, in, inertial, imu, c->parity, c->stream, nullptr);
+            st = enqueue_frame(c, in, inertial, imu, c->parity, c->stream, nullptr, !side);
         if (st != SF_OK) return st;
         if (c->learned)
             for (int s = 0; s < c->S; ++s) {
@@ -1289,6 +1350,15 @@ static sf_status push_frames(sf_ctx c, const void* const* Y, const void* const* 
         c->parity = 1 - c->parity;
         for (int s = 0; s < c->S; ++s) c->st[s].update_ran = true;
     }
+    if (ovl) {
+        // this frame's reads end here; the previous frame's inputs are free once the input
+        // stream has waited for its record
+        HIP_TRY(c, hipEventRecord(c->ev_step[c->mbuf], c->stream));
+        c->step_rec[c->mbuf] = true;
+        if (c->step_rec[1 - c->mbuf])
+            HIP_TRY(c, hipStreamWaitEvent(c->in_stream, c->ev_step[1 - c->mbuf], 0));
+    }
+    c->mbuf ^= 1;
     for (int s = 0; s < c->S; ++s) c->st[s].dt_prev = dt[s];
     c->frames += 1;
     return SF_OK;
@@ -1401,6 +1471,113 @@ sf_status sf_get_flow(sf_ctx c, int32_t kind, void* out) {
     if (st != SF_OK) return st;
     if (c->S != 1) return fail(c, SF_ERR_INVALID_ARG, "a batch context takes sf_get_flow_stream");
     return sf_get_flow_stream(c, 0, kind, out);
+}
+
+// -- mapping a camera's frame onto a stream's grid ------------------------------------------
+sf_status sf_set_source_camera(sf_ctx c, int32_t stream, const sf_camera* src, int32_t rows,
+                               int32_t cols) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    if (!src) return fail(c, SF_ERR_INVALID_ARG, "NULL camera");
+    if (!(src->fx > 0) || !(src->fy > 0) || !isfinite(src->fx) || !isfinite(src->fy) ||
+        !isfinite(src->cx) || !isfinite(src->cy))
+        return fail(c, SF_ERR_INVALID_ARG, "fx, fy must be finite and > 0, cx, cy finite");
+    if (src->eta) return fail(c, SF_ERR_INVALID_ARG, "the source camera is a pinhole (eta NULL)");
+    if (rows < 2 || cols < 2 || rows > (1 << 15) || cols > (1 << 15))
+        return fail(c, SF_ERR_INVALID_ARG, "source size must be in [2, 32768]");
+    StreamInfo& si = c->st[stream];
+    si.source = true;
+    si.src[0] = src->fx;
+    si.src[1] = src->fy;
+    si.src[2] = src->cx;
+    si.src[3] = src->cy;
+    si.src_rows = rows;
+    si.src_cols = cols;
+    return SF_OK;
+}
+
+sf_status sf_map_frame(sf_ctx c, int32_t stream, const void* Y_src, const void* rho_src,
+                       void* Y_out, void* rho_out) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    const StreamInfo& si = c->st[stream];
+    if (!c->camera) return fail(c, SF_ERR_STATE, "the cameras must be set before mapping");
+    if (!si.source) return fail(c, SF_ERR_STATE, "no source camera set for stream %d", stream);
+    if (!is_device_ptr(Y_src) || !is_device_ptr(rho_src) || !is_device_ptr(Y_out) ||
+        !is_device_ptr(rho_out))
+        return fail(c, SF_ERR_INVALID_ARG, "images must be device pointers");
+    MapArgs a{};
+    a.lv = c->lv_dev;
+    a.ent = si.e0;
+    a.fx = (float)si.src[0];
+    a.fy = (float)si.src[1];
+    a.cx = (float)si.src[2];
+    a.cy = (float)si.src[3];
+    a.rows = si.src_rows;
+    a.cols = si.src_cols;
+    a.Y = Y_src;
+    a.R = rho_src;
+    a.Yout = Y_out;
+    a.Rout = rho_out;
+    HIP_TRY(c, launch_map(c->storage, a, si.cfg.rows * si.cfg.cols, c->stream));
+    return SF_OK;
+}
+
+// -- inverse depth from a stereo pair ----------------------------------------------------------
+sf_status sf_set_stereo(sf_ctx c, int32_t stream, double baseline, int32_t max_disparity,
+                        int32_t iterations, double texture, double residual) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    if (!(baseline > 0.0) || !isfinite(baseline))
+        return fail(c, SF_ERR_INVALID_ARG, "baseline must be finite and > 0");
+    if (max_disparity < 0 || max_disparity > 64)
+        return fail(c, SF_ERR_INVALID_ARG, "max_disparity must be in [0, 64]");
+    if (iterations < 0 || iterations > 16)
+        return fail(c, SF_ERR_INVALID_ARG, "iterations must be in [0, 16]");
+    if (!(texture >= 0.0) || !isfinite(texture) || !(residual > 0.0) || !isfinite(residual))
+        return fail(c, SF_ERR_INVALID_ARG, "texture must be >= 0 and residual > 0, both finite");
+    StreamInfo& si = c->st[stream];
+    si.stereo = true;
+    si.baseline = baseline;
+    si.dmax = max_disparity;
+    si.iters = iterations;
+    si.texture = texture;
+    si.residual = residual;
+    return SF_OK;
+}
+
+sf_status sf_stereo_depth(sf_ctx c, int32_t stream, const void* Y_left, const void* Y_right,
+                          void* rho_out) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (stream < 0 || stream >= c->S) return fail(c, SF_ERR_INVALID_ARG, "stream out of range");
+    if (!c->camera) return fail(c, SF_ERR_STATE, "the cameras must be set first");
+    const StreamInfo& si = c->st[stream];
+    if (!si.stereo) return fail(c, SF_ERR_STATE, "no stereo parameters set for stream %d", stream);
+    if (c->lv[si.e0].geo && !c->grid_pinhole[stream])
+        return fail(c, SF_ERR_UNSUPPORTED, "stereo depth needs a pinhole stream (no eta grid)");
+    if (!is_device_ptr(Y_left) || !is_device_ptr(Y_right) || !is_device_ptr(rho_out))
+        return fail(c, SF_ERR_INVALID_ARG, "images must be device pointers");
+    StereoArgs a{};
+    a.YL = Y_left;
+    a.YR = Y_right;
+    a.rho = rho_out;
+    a.rows = si.cfg.rows;
+    a.cols = si.cfg.cols;
+    a.fx = (float)si.cam[0];
+    a.fy = (float)si.cam[1];
+    a.cx = (float)si.cam[2];
+    a.cy = (float)si.cam[3];
+    a.baseline = (float)si.baseline;
+    a.dmax = si.dmax;
+    a.iters = si.iters;
+    a.texture = (float)si.texture;
+    a.residual = (float)si.residual;
+    HIP_TRY(c, launch_stereo(c->storage, a, c->stream));
+    return SF_OK;
 }
 
 // -- state blob -----------------------------------------------------------------------------
@@ -1636,6 +1813,7 @@ sf_status sf_set_state(sf_ctx c, const void* host_blob, size_t bytes) {
 sf_status sf_destroy(sf_ctx c) {
     if (!c) return SF_OK;
     (void)hipStreamSynchronize(c->stream);
+    if (c->pyr_stream) (void)hipStreamSynchronize(c->pyr_stream);
     for (auto& m : c->marks) { (void)hipEventDestroy(m.a); (void)hipEventDestroy(m.b); }
     for (auto e : c->pool) (void)hipEventDestroy(e);
     if (c->arena) (void)hipFree(c->arena);
@@ -1645,6 +1823,9 @@ sf_status sf_destroy(sf_ctx c) {
     if (c->geo) (void)hipFree(c->geo);
     drop_graphs(c);
     if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->pyr_stream) (void)hipStreamDestroy(c->pyr_stream);
+    for (hipEvent_t e : {c->ev_in, c->ev_pyr, c->ev_step[0], c->ev_step[1]})
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return SF_OK;
 }

@@ -68,8 +68,8 @@ struct LevelDev {
     void* dw[2][3];                  // lower levels only
     void* rho[2];
     void* Y[2];
-    void* Ym;                        // pyramid image of this frame (levels >= 1)
-    void* Rm;                        // pyramid inverse depth of this frame (levels >= 1)
+    void* Ym[2];                     // pyramid image of a frame (levels >= 1), two buffers
+    void* Rm[2];                     // pyramid inverse depth, the same (FrameInputs::mbuf)
     // The prediction of a level may be split over several step launches ("passes") of at most
     // a few steps each, so that each pass needs a smaller halo.  A pass entry is a copy of its
     // level's entry with its own halo and tiles, and:
@@ -85,11 +85,15 @@ struct LevelDev {
 };
 
 // Per-frame arguments: the finest-level measurements of every stream (caller's device
-// pointers, pitch = cols) and the dt_new / dt_old rescale of w and dw.
+// pointers, pitch = cols), the dt_new / dt_old rescale of w and dw, and which of the two
+// pyramid buffers the frame's pyramid is written to and read from (consecutive frames
+// alternate, so that a frame's pyramid can be built while the previous frame's level step
+// still reads its own).
 struct FrameInputs {
     const void* Y[kMaxStreams];
     const void* R[kMaxStreams];
     float scale[kMaxStreams];
+    int mbuf;
 };
 
 // Camera rates of one stream for the inertial source terms of the prediction, in the filter's
@@ -124,6 +128,34 @@ struct ElemArgs {
     float inv_dts[kMaxStreams];      // their scale to rad/s
     FrameInputs in;
 };
+
+// Mapping of a pinhole camera's frame onto the finest grid of a stream (k_map): one thread per
+// grid pixel of entry `ent`.
+struct MapArgs {
+    const LevelDev* lv;
+    int ent;
+    float fx, fy, cx, cy;            // the source camera
+    int rows, cols;                  // its size
+    const void* Y;                   // source image and inverse depth (storage type, rows x cols)
+    const void* R;
+    void* Yout;                      // grid image and inverse depth (storage type, level size)
+    void* Rout;
+};
+hipError_t launch_map(int storage, const MapArgs& a, int pixels, hipStream_t s);
+
+// Inverse depth from a rectified stereo pair (k_stereo, sflow_stereo.hip): one thread per pixel
+// of the stream's finest level.
+struct StereoArgs {
+    const void* YL;                  // left (the filter's) and right images, storage type
+    const void* YR;
+    void* rho;                       // inverse-depth measurement out, storage type
+    int rows, cols;
+    float fx, fy, cx, cy;            // left pinhole camera
+    float baseline;                  // metres along the left camera's x axis
+    int dmax, iters;                 // search range [0, dmax] px, Gauss-Newton steps
+    float texture, residual;         // validity thresholds
+};
+hipError_t launch_stereo(int storage, const StereoArgs& a, hipStream_t s);
 
 // Device allocation of the library (hipMalloc, with a failure-injection hook for tests: the
 // environment variable SFLOW_FAIL_ALLOC=n fails the n-th allocation counted from the moment

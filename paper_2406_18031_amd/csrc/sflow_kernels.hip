@@ -639,8 +639,8 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
     // prediction: the new image at this wave's rows, the inverse depth at its rows and the rows
     // just above and below (clamped to the image; lanes outside it read column 0 and are
     // zeroed) -------------------------------------------------------------------------------
-    const T* Ymeas = (const T*)(h == 0 ? a.in.Y[L.stream] : L.Ym);
-    const T* Rmeas = (const T*)(h == 0 ? a.in.R[L.stream] : L.Rm);
+    const T* Ymeas = (const T*)(h == 0 ? a.in.Y[L.stream] : L.Ym[a.in.mbuf]);
+    const T* Rmeas = (const T*)(h == 0 ? a.in.R[L.stream] : L.Rm[a.in.mbuf]);
     const int mp = h == 0 ? C : L.pitch;
     float ypre[RPW], rpre[RPW + 2];
     if (L.pass_last) {
@@ -1014,8 +1014,9 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     ConstLevelDev& S = level_entry(a.lv, e - 1);
     ConstLevelDev& U = level_entry(a.lv, e + 1);
     const int urows = U.rows, ucols = U.cols, upitch = U.pitch;
-    T* const uYm = (T*)U.Ym;
-    T* const uRm = (T*)U.Rm;
+    const int mb = a.in.mbuf;
+    T* const uYm = (T*)U.Ym[mb];
+    T* const uRm = (T*)U.Rm[mb];
     const int ntx = (D.cols + TILE - 1) / TILE;
     const int ti0 = (t / ntx) * TILE, tj0 = (t % ntx) * TILE;
     const bool two = D.parent >= 0;
@@ -1033,8 +1034,8 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
     }
     const int nr = r1 - r0, nc = q1 - q0;
     const bool fin = S.level == 0;
-    const T* Ys = (const T*)(fin ? a.in.Y[D.stream] : S.Ym);
-    const T* Rs = (const T*)(fin ? a.in.R[D.stream] : S.Rm);
+    const T* Ys = (const T*)(fin ? a.in.Y[D.stream] : S.Ym[mb]);
+    const T* Rs = (const T*)(fin ? a.in.R[D.stream] : S.Rm[mb]);
     const int sp = fin ? S.cols : S.pitch;
     const int p = threadIdx.x;
     // the finer level's rows [s0, s0 + ns) and columns [u0, u0 + nu): every clamped tap
@@ -1075,8 +1076,8 @@ __global__ void __launch_bounds__(kPyrThreads) k_pyramid(ElemArgs a) {
         pY[li][lj] = rnd<T>(y);
         pR[li][lj] = rnd<T>(r);
         if (i >= ti0 && i < ti0 + TILE && j >= tj0 && j < tj0 + TILE) {
-            stv((T*)D.Ym, (size_t)i * D.pitch + j, y);
-            stv((T*)D.Rm, (size_t)i * D.pitch + j, r);
+            stv((T*)D.Ym[mb], (size_t)i * D.pitch + j, y);
+            stv((T*)D.Rm[mb], (size_t)i * D.pitch + j, r);
         }
     }
     if (!two) return;
@@ -1100,8 +1101,8 @@ __global__ void __launch_bounds__(kElemBlock) k_init(ElemArgs a) {
     if (!elem_pixel(a, k0, e, i, j)) return;
     ConstLevelDev& L = level_entry(a.lv, e);
     const bool fin = L.level == 0;
-    const T* Ym = (const T*)(fin ? a.in.Y[L.stream] : L.Ym);
-    const T* Rm = (const T*)(fin ? a.in.R[L.stream] : L.Rm);
+    const T* Ym = (const T*)(fin ? a.in.Y[L.stream] : L.Ym[a.in.mbuf]);
+    const T* Rm = (const T*)(fin ? a.in.R[L.stream] : L.Rm[a.in.mbuf]);
     const int mp = fin ? L.cols : L.pitch;
     // same separable order of operations as the image model of k_step, so that a static
     // scene reproduces Yhat bit for bit
@@ -1495,6 +1496,65 @@ __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     a.out[(kLearnFB + 6) * npx + o] = pixel_dmu(L, i, j);
 }
 
+// ------------------------------------------------------------------------------------------
+// mapping a pinhole camera's frame onto a stream's finest grid (Section "Experimental
+// Validation": the image and depth are mapped onto the grid before the filter runs).  Grid
+// direction eta projects to source pixel (u, v) = (fx eta_x / eta_z + cx, fy eta_y / eta_z + cy);
+// brightness is interpolated bilinearly with the source clamped to its edge; inverse depth
+// bilinearly over the valid (not NaN) neighbours, missing when they carry less than half of
+// the weight or the direction is more than 1e-3 px outside the image or behind the camera.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kElemBlock) k_map(MapArgs a) {
+    ConstLevelDev& L = level_entry(a.lv, a.ent);
+    const int p = blockIdx.x * kElemBlock + threadIdx.x;
+    if (p >= L.rows * L.cols) return;
+    const int i = p / L.cols, j = p - i * L.cols;
+    float ex, ey, ez;
+    if (L.geo) {
+        const size_t gp = (size_t)L.rows * L.gpitch, go = (size_t)i * L.gpitch + j;
+        ex = L.geo[6 * gp + go];
+        ey = L.geo[7 * gp + go];
+        ez = L.geo[8 * gp + go];
+    } else {
+        const float x = fmaf((float)j, L.ifx, -L.cxn), y = fmaf((float)i, L.ify, -L.cyn);
+        const float rinv = rsqrtf(fmaf(x, x, fmaf(y, y, 1.0f)));
+        ex = x * rinv;
+        ey = y * rinv;
+        ez = rinv;
+    }
+    const bool ahead = ez > 0.0f;
+    const float iz = ahead ? 1.0f / ez : 0.0f;
+    const float u = ahead ? fmaf(a.fx, ex * iz, a.cx) : 0.0f;
+    const float v = ahead ? fmaf(a.fy, ey * iz, a.cy) : 0.0f;
+    const float tol = 1e-3f;
+    const bool inside = ahead && u >= -tol && u <= (float)(a.cols - 1) + tol && v >= -tol &&
+                        v <= (float)(a.rows - 1) + tol;
+    const float uc = fminf(fmaxf(u, 0.0f), (float)(a.cols - 1));
+    const float vc = fminf(fmaxf(v, 0.0f), (float)(a.rows - 1));
+    const int j0 = min((int)uc, a.cols - 1), i0 = min((int)vc, a.rows - 1);
+    const int j1 = min(j0 + 1, a.cols - 1), i1 = min(i0 + 1, a.rows - 1);
+    const float fu = uc - (float)j0, fv = vc - (float)i0;
+    const float w[4] = {(1.0f - fv) * (1.0f - fu), (1.0f - fv) * fu, fv * (1.0f - fu), fv * fu};
+    const size_t o[4] = {(size_t)i0 * a.cols + j0, (size_t)i0 * a.cols + j1,
+                         (size_t)i1 * a.cols + j0, (size_t)i1 * a.cols + j1};
+    const T* Y = (const T*)a.Y;
+    const T* R = (const T*)a.R;
+    float yv = 0.0f, num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        yv = fmaf(w[k], ldv(Y, o[k]), yv);
+        const float r = ldv(R, o[k]);
+        if (!isnan(r)) {
+            num = fmaf(w[k], r, num);
+            den += w[k];
+        }
+    }
+    const size_t q = (size_t)p;
+    stv((T*)a.Yout, q, yv);
+    stv((T*)a.Rout, q, (inside && den >= 0.5f) ? num / den : __int_as_float(0x7fc00000));
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -1546,6 +1606,16 @@ hipError_t launch_pyramid(int storage, int tile, const ElemArgs& a, hipStream_t 
         else
             hipLaunchKernelGGL((k_pyramid<float, kTile2>), g, b, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_map(int storage, const MapArgs& a, int pixels, hipStream_t s) {
+    const int blocks = (pixels + kElemBlock - 1) / kElemBlock;
+    if (blocks == 0) return hipSuccess;
+    if (storage == SF_FP16)
+        hipLaunchKernelGGL(k_map<__half>, dim3(blocks), dim3(kElemBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_map<float>, dim3(blocks), dim3(kElemBlock), 0, s, a);
     return hipGetLastError();
 }
 

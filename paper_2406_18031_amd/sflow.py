@@ -91,7 +91,14 @@ def _load():
         "sf_set_tile": (st, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "sf_set_timing": (st, [vp, ctypes.c_int32]),
         "sf_set_graph": (st, [vp, ctypes.c_int32]),
+        "sf_set_input_stream": (st, [vp, vp]),
         "sf_copy_probe": (st, [vp, vp, ctypes.c_size_t, vp]),
+        "sf_set_source_camera": (st, [vp, ctypes.c_int32, ctypes.POINTER(sf_camera),
+                                      ctypes.c_int32, ctypes.c_int32]),
+        "sf_map_frame": (st, [vp, ctypes.c_int32, vp, vp, vp, vp]),
+        "sf_set_stereo": (st, [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                               ctypes.c_int32, ctypes.c_double, ctypes.c_double]),
+        "sf_stereo_depth": (st, [vp, ctypes.c_int32, vp, vp, vp]),
         "sf_set_pass_steps": (st, [vp, ctypes.c_int32]),
         "sf_kernel_times": (st, [vp, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
@@ -138,7 +145,8 @@ EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_st
             "sf_get_update_inputs", "sf_net_create", "sf_net_set_params", "sf_net_get_params",
             "sf_net_forward", "sf_net_train_step", "sf_net_set_loss", "sf_net_destroy",
             "sf_net_last_error", "sf_net_forward_noalloc", "sf_push_frame_ex",
-            "sf_push_frames_ex", "sf_set_graph", "sf_copy_probe")
+            "sf_push_frames_ex", "sf_set_graph", "sf_copy_probe", "sf_set_source_camera",
+            "sf_map_frame", "sf_set_stereo", "sf_stereo_depth", "sf_set_input_stream")
 
 
 def _check(status: int, ctx) -> None:
@@ -262,8 +270,36 @@ def sf_copy_probe(src, dst, nbytes: int, stream=None) -> None:
         raise SflowError(st, "sf_copy_probe")
 
 
+def sf_set_source_camera(ctx: int, stream: int, fx: float, fy: float, cx: float, cy: float,
+                         rows: int, cols: int) -> None:
+    cam = sf_camera(fx, fy, cx, cy, None)
+    _check(lib.sf_set_source_camera(ctx, stream, ctypes.byref(cam), rows, cols), ctx)
+
+
+def sf_map_frame(ctx: int, stream: int, Y_src, rho_src, Y_out, rho_out) -> None:
+    _check(lib.sf_map_frame(ctx, stream, _ptr(Y_src), _ptr(rho_src), _ptr(Y_out),
+                            _ptr(rho_out)), ctx)
+
+
+def sf_set_stereo(ctx: int, stream: int, baseline: float, max_disparity: int,
+                  iterations: int = 3, texture: float = 2.5e-3, residual: float = 0.05) -> None:
+    _check(lib.sf_set_stereo(ctx, stream, float(baseline), int(max_disparity), int(iterations),
+                             float(texture), float(residual)), ctx)
+
+
+def sf_stereo_depth(ctx: int, stream: int, Y_left, Y_right, rho_out) -> None:
+    _check(lib.sf_stereo_depth(ctx, stream, _ptr(Y_left), _ptr(Y_right), _ptr(rho_out)), ctx)
+
+
 def sf_set_graph(ctx: int, enable: bool) -> None:
     _check(lib.sf_set_graph(ctx, 1 if enable else 0), ctx)
+
+
+def sf_set_input_stream(ctx: int, stream) -> None:
+    """stream: a torch.cuda.Stream, a raw hipStream_t value, or None (the context stream)."""
+    if stream is not None and not isinstance(stream, int):
+        stream = stream.cuda_stream
+    _check(lib.sf_set_input_stream(ctx, ctypes.c_void_p(stream) if stream else None), ctx)
 
 
 def sf_kernel_times(ctx: int, reset: bool = False):
@@ -509,6 +545,36 @@ class Filter:
         sf_get_update_inputs(self.ctx, 0, out)
         return out
 
+    def set_stereo(self, baseline, max_disparity, iterations=3, texture=2.5e-3, residual=0.05):
+        sf_set_stereo(self.ctx, 0, baseline, max_disparity, iterations, texture, residual)
+
+    def set_input_stream(self, stream):
+        """The stream the pushed frames are produced on (None: the context stream)."""
+        sf_set_input_stream(self.ctx, stream)
+
+    def stereo_depth(self, Y_left, Y_right, rho_out=None):
+        """The inverse-depth measurement of the left image from the rectified pair."""
+        import torch
+        if rho_out is None:
+            dt = torch.float16 if self.storage == SF_FP16 else torch.float32
+            rho_out = torch.empty((self.rows, self.cols), dtype=dt, device="cuda")
+        sf_stereo_depth(self.ctx, 0, Y_left, Y_right, rho_out)
+        return rho_out
+
+    def set_source_camera(self, fx, fy, cx, cy, rows, cols):
+        sf_set_source_camera(self.ctx, 0, fx, fy, cx, cy, rows, cols)
+
+    def map(self, Y_src, rho_src, Y_out=None, rho_out=None):
+        """One source-camera frame resampled onto the grid: (Y, rho) tensors of the grid."""
+        import torch
+        dt = torch.float16 if self.storage == SF_FP16 else torch.float32
+        if Y_out is None:
+            Y_out = torch.empty((self.rows, self.cols), dtype=dt, device="cuda")
+        if rho_out is None:
+            rho_out = torch.empty((self.rows, self.cols), dtype=dt, device="cuda")
+        sf_map_frame(self.ctx, 0, Y_src, rho_src, Y_out, rho_out)
+        return Y_out, rho_out
+
     def get_state(self):
         return unpack_state(sf_get_state(self.ctx), self.rows, self.cols, self.levels)
 
@@ -585,6 +651,10 @@ class Batch:
         self.ctx = sf_create_batch(cfgs, stream)
         sf_set_cameras(self.ctx, [tuple(sp["camera"]) + ((sp["eta"],) if sp.get("eta") is not None
                                                          else ()) for sp in self.specs])
+
+    def set_input_stream(self, stream):
+        """The stream the pushed frames are produced on (None: the context stream)."""
+        sf_set_input_stream(self.ctx, stream)
 
     def push(self, Ys, rhos, dts, omegas=None, accs=None, omega_dots=None):
         if omegas is None and accs is None and omega_dots is None:
