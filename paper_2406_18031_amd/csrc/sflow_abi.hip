@@ -998,18 +998,13 @@ static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias
 // network on the finest level of every stream, then the per-pixel choice, smoothing and store
 static sf_status run_learned(sf_ctx c, int q, hipStream_t strm) {
     const int P = c->segs.total;
-    for (int l = 0; l < kCnnLayers; ++l) {
-        ConvArgs a{};
-        a.segs = c->segs;
-        a.in = l == 0 ? c->lpack : c->act[l & 1];   // layer 0: the input the level step packed
-        a.w = c->wf + (size_t)l * 9 * 256;
-        a.bias = c->cnn_bias + l * 16;
-        a.relu = l < kCnnLayers - 1;
-        a.nout = l < kCnnLayers - 1 ? 16 : 3;
-        a.out = c->act[(l + 1) & 1];
-        a.out_f32 = c->lbuf + (size_t)kLearnOut * P;
-        HIP_TRY(c, launch_conv(a, l == kCnnLayers - 1, strm));
-    }
+    NetArgs a{};   // the four layers in one launch, on the input the level step packed
+    a.segs = c->segs;
+    a.in = c->lpack;
+    a.w = c->wf;
+    a.bias = c->cnn_bias;
+    a.out_f32 = c->lbuf + (size_t)kLearnOut * P;
+    HIP_TRY(c, launch_net(a, strm));
     CombineArgs cb{};
     cb.lv = c->lv_dev;
     cb.parity = q;

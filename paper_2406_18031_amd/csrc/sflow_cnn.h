@@ -35,6 +35,17 @@ struct ConvArgs {
     int tblk[kCnnMaxSegs + 1];   // first block of each image's 16 x 16 tiles (set by launch_conv)
 };
 
+// The whole forward pass in one launch (k_net): input BF16 NHWC 16 (9 used), the packed
+// forward weights and biases of the four layers, output FP32 planes [3][total].
+struct NetArgs {
+    CnnSegs segs;
+    const uint16_t* in;
+    const uint16_t* w;       // BF16 [4][9][16 out][16 in]
+    const float* bias;       // FP32 [4][16]
+    float* out_f32;
+    int tblk[kCnnMaxSegs + 1];   // first block of each image's tiles (set by launch_net)
+};
+
 struct DwArgs {
     CnnSegs segs;
     const uint16_t* in;      // layer input, BF16 NHWC 16
@@ -80,6 +91,7 @@ struct GradArgs {
 };
 
 hipError_t launch_conv(const ConvArgs& a, bool out_f32, hipStream_t s);
+hipError_t launch_net(const NetArgs& a, hipStream_t s);
 hipError_t launch_conv_dw(const DwArgs& a, hipStream_t s);
 hipError_t launch_loss(const LossArgs& a, hipStream_t s);
 hipError_t launch_pack_inputs(const float* in, int C, int total, uint16_t* out, hipStream_t s);

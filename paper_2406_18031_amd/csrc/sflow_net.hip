@@ -293,8 +293,15 @@ sf_status sf_net_forward(sf_net n, const float* in, float* out) {
     if (!n->has_params) return nfail(n, SF_ERR_STATE, "no parameters set");
     if (!dev_ptr(in) || !dev_ptr(out)) return nfail(n, SF_ERR_INVALID_ARG, "in and out must be device pointers");
     NET_TRY(n, launch_planes_in(n->segs, in, kCnnInputs, n->in, n->stream));
-    st = forward(n);
-    if (st != SF_OK) return st;
+    // inference: the four layers in one launch (bitwise the layer-by-layer pass of training)
+    NET_TRY(n, launch_pack_inputs(n->in, kCnnInputs, n->segs.total, n->act[0], n->stream));
+    NetArgs a{};
+    a.segs = n->segs;
+    a.in = n->act[0];
+    a.w = n->wf;
+    a.bias = n->bias;
+    a.out_f32 = n->out;
+    NET_TRY(n, launch_net(a, n->stream));
     NET_TRY(n, launch_planes_out(n->segs, n->out, 3, out, n->stream));
     return SF_OK;
 }
@@ -419,8 +426,8 @@ sf_status sf_net_forward_noalloc(const float* params, int32_t rows, int32_t cols
     if (e == hipSuccess) e = launch_planes_in(sg, in, kCnnInputs, planes_in, s);
     if (e == hipSuccess) e = launch_pack_inputs(planes_in, kCnnInputs, sg.total, act[0], s);
     for (int l = 0; l < kCnnLayers && e == hipSuccess; ++l) {
-        // the layers of sf_net_forward's forward pass, activations ping-ponging between two
-        // buffers (inference keeps no layer inputs for a backward pass)
+        // one launch per layer (the sequence training runs; sf_net_forward's single launch
+        // gives bitwise the same), activations ping-ponging between two buffers
         ConvArgs a{};
         a.segs = sg;
         a.in = act[l & 1];

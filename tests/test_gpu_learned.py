@@ -106,6 +106,32 @@ def test_network_gradients_match_oracle():
     net.close()
 
 
+def test_fused_forward_equals_the_layer_by_layer_pass():
+    """sf_net_forward runs the four layers in one launch (24 x 58 output tiles, activations in
+    LDS); training runs them one launch each.  With the fused output as the training target the
+    layer-by-layer output's endpoint loss has a derivative of exactly zero at every pixel, so
+    the weight gradient is exactly zero if and only if the two outputs agree bit for bit (a
+    one-ulp change of one target value makes it nonzero).  Images of several tiles with ragged
+    tails, one exactly a tile, one pixel, one taller than wide."""
+    import torch
+    from paper_2406_18031_amd import sflow
+    log("fused forward against the layer-by-layer pass")
+    rng = np.random.default_rng(8)
+    sizes = [(61, 130), (24, 58), (1, 1), (100, 59), (25, 117)]
+    flat = _flat(_params(5))
+    net = sflow.Net(sizes, flat)
+    x = _cat(_images(rng, 9, sizes))
+    out = net.forward(x).clone()
+    assert bool(torch.isfinite(out).all())
+    _, grad = net.train_step(x, out, 0.0, want_grad=True)
+    assert np.all(grad == 0.0), float(np.abs(grad).max())
+    bumped = out.clone()
+    bumped[1234] = torch.nextafter(bumped[1234], torch.tensor(np.inf, device="cuda"))
+    _, grad = net.train_step(x, bumped, 0.0, want_grad=True)
+    assert np.any(grad != 0.0)
+    net.close()
+
+
 def test_training_reduces_loss():
     from oracle import cnn
     from paper_2406_18031_amd import learned, sflow
