@@ -997,29 +997,17 @@ static PackArgs pack_args(float* params, uint16_t* wf, uint16_t* wb, float* bias
 
 // network on the finest level of every stream, then the per-pixel choice, smoothing and store
 static sf_status run_learned(sf_ctx c, int q, hipStream_t strm) {
-    const int P = c->segs.total;
-    NetArgs a{};   // the four layers in one launch, on the input the level step packed
-    a.segs = c->segs;
-    a.in = c->lpack;
-    a.w = c->wf;
-    a.bias = c->cnn_bias;
-    a.out_f32 = c->lbuf + (size_t)kLearnOut * P;
-    HIP_TRY(c, launch_net(a, strm));
-    CombineArgs cb{};
-    cb.lv = c->lv_dev;
-    cb.parity = q;
-    cb.threshold = c->threshold;
-    cb.fallbacks = c->fallbacks;
-    int b = 0;
-    for (int s = 0; s < c->S; ++s) {
-        const LevelDev& L = c->lv[c->st[s].e0];
-        cb.ent[cb.n] = c->st[s].e0;
-        cb.blk[cb.n] = b;
-        b += ((L.rows + 31) / 32) * ((L.cols + 31) / 32);
-        ++cb.n;
-    }
-    cb.blk[cb.n] = b;
-    HIP_TRY(c, launch_combine(c->storage, cb, strm));
+    NetCombineArgs a{};   // the network on the input the level step packed, then the choice
+    a.net.segs = c->segs;
+    a.net.in = c->lpack;
+    a.net.w = c->wf;
+    a.net.bias = c->cnn_bias;
+    a.lv = c->lv_dev;
+    for (int s = 0; s < c->S; ++s) a.ent[s] = c->st[s].e0;
+    a.parity = q;
+    a.threshold = c->threshold;
+    a.fallbacks = c->fallbacks;
+    HIP_TRY(c, launch_net_combine(c->storage, a, strm));
     return SF_OK;
 }
 

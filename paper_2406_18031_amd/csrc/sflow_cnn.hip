@@ -18,19 +18,16 @@
 #include <atomic>
 
 #include "sflow_cnn.h"
+#include "sflow_net_tile.h"
 
 namespace sflow {
 namespace {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ float bf2f(uint16_t v) {
-    return __builtin_bit_cast(float, (uint32_t)v << 16);
-}
-__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (v_cvt_pk_bf16_f32)
-    return __builtin_bit_cast(uint16_t, (__bf16)f);
-}
+using nettile::s4;
+using nettile::f4;
+using nettile::bf2f;
+using nettile::f2bf;
+using nettile::unpack4;
 
 // the image a 16-pixel group belongs to
 __device__ __forceinline__ int find_seg(const CnnSegs& s, int p) {
@@ -44,15 +41,6 @@ __device__ __forceinline__ int find_seg(const CnnSegs& s, int p) {
 // optionally masked) in LDS, and each wave computes 4 rows of 16 pixels x 16 output channels,
 // nine MFMAs per row (one per tap) with the weights held in registers.
 constexpr int kConvTile = 16, kConvPatch = kConvTile + 2;
-
-__device__ __forceinline__ s4 unpack4(uint2 v) {
-    s4 r;
-    r[0] = (short)(v.x & 0xffff);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xffff);
-    r[3] = (short)(v.y >> 16);
-    return r;
-}
 
 template <bool OUT_F32>
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
@@ -148,149 +136,20 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     }
 }
 
-// The four layers in one launch (inference: no layer input is kept).  A block of 12 waves
-// computes a kNetTH x kNetTW tile of one image's output (two blocks fit a CU's LDS).  It stages the input over the tile
-// plus a 4-pixel margin (zero outside the image) in LDS; layer l = 0..3 then computes its
-// output over the tile plus a (3 - l)-pixel margin from the other LDS buffer, setting the
-// values outside the image to 0 (the zero padding the next layer reads); the last layer's three
-// FP32 channels leave through LDS.  Each 16-pixel output row segment takes the nine MFMAs of
-// k_conv in the same tap order with the operands' roles exchanged (weights as A, activations
-// as B: D is the transposed product, each element the same sum of the same exact BF16
-// products), then the same bias, ReLU and rounding, so the result is bitwise that of the four
-// k_conv launches.  With the exchanged roles a lane receives four consecutive channels of one
-// pixel and stores them with one 8-byte LDS write.
-// Waves: wave w takes the 16 output columns 16 (w % 3) .. + 15 of a layer's region (3 x 16 =
-// 48 >= its width) and a quarter of its rows, two rows at a time (two independent MFMA
-// chains), sliding down them with the B operands of the input rows they read held in
-// registers, so each input row is read from LDS once per wave.
-constexpr int kNetTH = 16, kNetTW = 42;        // output tile
-constexpr int kNetSegs = 3;                    // 16-pixel segments per region row (48 >= TW + 6)
-constexpr int kNetWaves = kNetSegs * 4;        // a segment and a quarter of the rows each
-constexpr int kNetThreads = 64 * kNetWaves;
-constexpr int kNetPitch = 50;                  // LDS row pitch in pixels: TW + 8, and 32 + 15 + 2 < it
-constexpr int kNetRowsX = kNetTH + 8;          // buffer X: the input (24 rows), layer 1's output (20)
-constexpr int kNetRowsY = kNetTH + 6;          // buffer Y: layer 0's output (22), layer 2's output (18)
-constexpr size_t kNetLds = (size_t)(kNetRowsX + kNetRowsY) * kNetPitch * 32;   // 73 600 bytes: two blocks per CU
-static_assert(kNetTW + 8 == kNetPitch && 16 * (kNetSegs - 1) + 15 + 2 < kNetPitch &&
-              kNetTW + 6 <= 16 * kNetSegs, "the segments cover every layer's region width");
-static_assert(3 * kNetTH * kNetTW * 4 <= kNetRowsX * kNetPitch * 32, "output staging fits in X");
-
-__global__ void __launch_bounds__(kNetThreads) k_net(NetArgs a) {
+// The four layers in one launch (inference): one block per 16 x 42 output tile of one image
+// (nettile::net_tile), bitwise the four k_conv launches.
+__global__ void __launch_bounds__(nettile::kNetThreads) k_net(NetArgs a) {
     extern __shared__ uint2 net_lds[];
-    uint2* const X = net_lds;                                  // [row][pixel][channel quad]
-    uint2* const Y = net_lds + (size_t)kNetRowsX * kNetPitch * 4;
     const int b = blockIdx.x;
     int sgi = 0;
     while (sgi + 1 < a.segs.n && a.tblk[sgi + 1] <= b) ++sgi;
     const int base = a.segs.base[sgi], rows = a.segs.rows[sgi], cols = a.segs.cols[sgi];
     const int t = b - a.tblk[sgi];
+    using namespace nettile;
     const int tiles_x = (cols + kNetTW - 1) / kNetTW;
     const int ty0 = (t / tiles_x) * kNetTH, tx0 = (t % tiles_x) * kNetTW;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int col = lane & 15;           // A row: output channel; B column, D column: pixel
-    const int quad = lane >> 4;          // A/B k block: input channels 4 quad .. +3; D rows:
-                                         // output channels 4 quad .. +3
-    {   // the input over the tile and a 4-pixel margin: 16-byte chunks, every load in flight
-        // together (addresses outside the image read the first pixel and are zeroed)
-        constexpr int NQ = kNetRowsX * kNetPitch * 2, NL = (NQ + kNetThreads - 1) / kNetThreads;
-        uint4 vv[NL];
-        bool inb[NL];
-#pragma unroll
-        for (int m = 0; m < NL; ++m) {
-            const int q = threadIdx.x + kNetThreads * m;
-            const int px = q >> 1, half = q & 1;
-            const int yy = ty0 - 4 + px / kNetPitch, xx = tx0 - 4 + px % kNetPitch;
-            inb[m] = q < NQ && yy >= 0 && yy < rows && xx >= 0 && xx < cols;
-            const size_t off = inb[m] ? ((size_t)base + (size_t)yy * cols + xx) * 16 + half * 8 : 0;
-            vv[m] = *(const uint4*)(a.in + off);
-        }
-        uint4* X4 = reinterpret_cast<uint4*>(X);
-#pragma unroll
-        for (int m = 0; m < NL; ++m) {
-            const int q = threadIdx.x + kNetThreads * m;
-            if (q < NQ) X4[q] = inb[m] ? vv[m] : make_uint4(0u, 0u, 0u, 0u);
-        }
-    }
-    float* const out32 = reinterpret_cast<float*>(X);         // [3][TH][TW], after layer 2
-    const int x0 = 16 * (wave % kNetSegs);
-    const int px = x0 + col;                                  // this lane's output pixel column
-    for (int l = 0; l < kCnnLayers; ++l) {
-        const uint2* src = (l & 1) ? Y : X;
-        uint2* dst = (l & 1) ? X : Y;
-        const int halo = 3 - l;                                // margin of this layer's output
-        const int R = kNetTH + 2 * halo, W = kNetTW + 2 * halo;
-        const int rq = wave / kNetSegs;
-        const int r0 = rq * R / 4, r1 = (rq + 1) * R / 4;
-        s4 wv[9];
-#pragma unroll
-        for (int tp = 0; tp < 9; ++tp)
-            wv[tp] = unpack4(*(const uint2*)(a.w + (((size_t)l * 9 + tp) * 16 + col) * 16 + 4 * quad));
-        float bias[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) bias[k] = a.bias[l * 16 + 4 * quad + k];
-        const int gx = tx0 - halo + px;
-        const bool col_in = px < W && gx >= 0 && gx < cols;
-        __syncthreads();   // the previous layer's output (or the staged input) is complete
-        auto load_row = [&](s4 (&g)[3], int row) {
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-                g[dx] = unpack4(src[((size_t)row * kNetPitch + x0 + col + dx) * 4 + quad]);
-        };
-        // output row r: D[4 quad + k][col] is channel 4 quad + k of pixel px
-        auto store_row = [&](int r, const f4& acc) {
-            if (l < kCnnLayers - 1) {
-                const int gy = ty0 - halo + r;
-                const bool in = col_in && gy >= 0 && gy < rows;
-                uint16_t h[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) h[k] = in ? f2bf(fmaxf(acc[k] + bias[k], 0.0f)) : (uint16_t)0;
-                dst[((size_t)r * kNetPitch + px) * 4 + quad] =
-                    make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-            } else if (quad == 0 && px < kNetTW) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) out32[(k * kNetTH + r) * kNetTW + px] = acc[k] + bias[k];
-            }
-        };
-        // B operands of the input rows r .. r + 3 (output rows r, r + 1 read r .. r + 2 and
-        // r + 1 .. r + 3), columns x0 + col + 0..2
-        s4 f[4][3];
-        if (r0 < r1) {
-            load_row(f[0], r0);
-            load_row(f[1], r0 + 1);
-        }
-        int r = r0;
-        for (; r + 1 < r1; r += 2) {
-            load_row(f[2], r + 2);
-            load_row(f[3], r + 3);
-            f4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wv[dy * 3 + dx], f[dy][dx], acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wv[dy * 3 + dx], f[dy + 1][dx], acc1, 0, 0, 0);
-                }
-            store_row(r, acc0);
-            store_row(r + 1, acc1);
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                f[0][dx] = f[2][dx];
-                f[1][dx] = f[3][dx];
-            }
-        }
-        if (r < r1) {   // an odd row left
-            load_row(f[2], r + 2);
-            f4 acc0 = {0, 0, 0, 0};
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx)
-                    acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wv[dy * 3 + dx], f[dy][dx], acc0, 0, 0, 0);
-            store_row(r, acc0);
-        }
-    }
-    __syncthreads();
+    net_tile(a.in, a.w, a.bias, base, rows, cols, ty0, tx0, net_lds);
+    const float* out32 = reinterpret_cast<const float*>(net_lds);
     for (int p = threadIdx.x; p < kNetTH * kNetTW; p += kNetThreads) {
         const int y = ty0 + p / kNetTW, x = tx0 + p % kNetTW;
         if (y >= rows || x >= cols) continue;
@@ -538,7 +397,7 @@ hipError_t launch_net(const NetArgs& args, hipStream_t s) {
     const uint64_t bit = 1ull << (dev & 63);
     if (!(prepared.load() & bit)) {
         e = hipFuncSetAttribute((const void*)k_net, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)kNetLds);
+                                (int)nettile::kNetLds);
         if (e != hipSuccess) return e;
         prepared.fetch_or(bit);
     }
@@ -546,11 +405,12 @@ hipError_t launch_net(const NetArgs& args, hipStream_t s) {
     int blocks = 0;
     for (int k = 0; k < a.segs.n; ++k) {
         a.tblk[k] = blocks;
-        blocks += ((a.segs.rows[k] + kNetTH - 1) / kNetTH) * ((a.segs.cols[k] + kNetTW - 1) / kNetTW);
+        blocks += ((a.segs.rows[k] + nettile::kNetTH - 1) / nettile::kNetTH) *
+                  ((a.segs.cols[k] + nettile::kNetTW - 1) / nettile::kNetTW);
     }
     a.tblk[a.segs.n] = blocks;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_net, dim3(blocks), dim3(kNetThreads), kNetLds, s, a);
+    hipLaunchKernelGGL(k_net, dim3(blocks), dim3(nettile::kNetThreads), nettile::kNetLds, s, a);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "sflow.h"
+#include "sflow_cnn.h"
 
 namespace sflow {
 
@@ -32,8 +33,8 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 
 // Planes of the learned-update buffers of a finest level, each `ltotal` floats: 9 unused (the
 // network's 9 inputs go to `lpack`, BF16), prior x0 (3), least-squares solution (3), cost terms
-// a_Y (3), a_rho (3), G1, G2 (2), the network's output (3), the smoothed solution (3) and the
-// applied correction (3).
+// a_Y (3), a_rho (3), G1, G2 (2), 3 unused (the network's output stays in LDS: the network and
+// the choice run in one launch), the smoothed solution (3) and the applied correction (3).
 constexpr int kLearnInputs = 9;
 constexpr int kLearnX0 = 9, kLearnXP = 12, kLearnFB = 15, kLearnOut = 23;
 constexpr int kLearnXS = 26;      // smoothed least-squares solution (the state)
@@ -181,17 +182,18 @@ hipError_t prepare_kernels(size_t max_lds_bytes);
 // step), 0 = none (the other kernels' arguments do not change from frame to frame).
 int frame_input_kind(const void* func);
 
-// learned update: choose between the network's and the least-squares solution per pixel,
-// smooth, store the finest level's new flow state (one launch for all streams)
-struct CombineArgs {
+// learned update, one launch for all streams: the network on every stream's finest level
+// (net: its images are the streams' finest levels, in stream order), then the choice between
+// the network's and the least-squares solution per pixel, the smoothing and the store of the
+// finest level's new flow state
+struct NetCombineArgs {
+    NetArgs net;
     const LevelDev* lv;
-    int n;
-    int ent[kMaxStreams];
-    int blk[kMaxStreams + 1];        // blocks of 32 x 32 output pixels per entry
+    int ent[kMaxStreams];            // the finest level's entry of image k
     int parity;                      // state parity written
     float threshold;                 // fallback when the cost increase exceeds it
     unsigned long long* fallbacks;   // accumulated count of pixels that fell back
 };
-hipError_t launch_combine(int storage, const CombineArgs& a, hipStream_t s);
+hipError_t launch_net_combine(int storage, const NetCombineArgs& a, hipStream_t s);
 
 }  // namespace sflow

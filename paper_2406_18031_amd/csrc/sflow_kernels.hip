@@ -17,7 +17,10 @@
 // with only the strip-boundary rows exchanged through LDS (one barrier per step).  Geometry
 // (unit ray, tangent basis, pixel spacing) is recomputed from the pinhole intrinsics in
 // registers instead of being read from memory.
+#include <atomic>
+
 #include "sflow_internal.h"
+#include "sflow_net_tile.h"
 
 namespace sflow {
 namespace {
@@ -1334,60 +1337,68 @@ __global__ void __launch_bounds__(kElemBlock) k_output(ElemArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
-// learned update: the level's N_s passes of 5x5 averaging of the least-squares solution x_ls
-// (same order of operations as in k_step) and the state store, as in the plain update; then,
-// per pixel, the network's correction dmu * c of the output flow, kept unless its
-// least-squares cost G1 (aY.c)^2 + G2 (aR.c)^2 + g3 |c|^2 exceeds the threshold (or is not
-// finite).  The correction is applied to the output (k_output), not fed back into the state.
-// One block = 32 x 32 output pixels plus a halo of 2 N_s (N_s <= 4).
+// learned update, one launch: per 16 x 42 tile of a stream's finest level, the network
+// (nettile::net_tile, bitwise the per-layer launches) and then, with its output still in LDS,
+// the level's N_s passes of 5x5 averaging of the least-squares solution x_ls (same order of
+// operations as in k_step) and the state store, as in the plain update; then, per pixel, the
+// network's correction dmu * c of the output flow, kept unless its least-squares cost
+// G1 (aY.c)^2 + G2 (aR.c)^2 + g3 |c|^2 exceeds the threshold (or is not finite).  The
+// correction is applied to the output (k_output, k_reconstruct), not fed back into the state.
+// The averaging region is the tile plus a halo of 2 N_s (N_s <= 4), in the LDS the network
+// has finished with.
 // ------------------------------------------------------------------------------------------
-constexpr int kCombTile = 32;
-constexpr int kCombMaxRegion = kCombTile + 2 * 2 * 4;
+constexpr int kCombPlane = (nettile::kNetTH + 16) * (nettile::kNetTW + 16);
+static_assert((3 * nettile::kNetTH * nettile::kNetTW + 2 * 3 * kCombPlane) * sizeof(float) <=
+              nettile::kNetLds, "the averaging region fits in the network's LDS");
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
-    __shared__ float X[3][kCombMaxRegion * kCombMaxRegion];
-    __shared__ float TM[3][kCombMaxRegion * kCombMaxRegion];
+__global__ void __launch_bounds__(nettile::kNetThreads) k_net_combine(NetCombineArgs a) {
+    using namespace nettile;
+    constexpr int TH = kNetTH, TW = kNetTW, NT = kNetThreads;
+    extern __shared__ uint2 net_lds[];
     __shared__ unsigned int nfb;
     const int b = blockIdx.x;
     int k = 0;
-    while (k + 1 < a.n && a.blk[k + 1] <= b) ++k;
+    while (k + 1 < a.net.segs.n && a.net.tblk[k + 1] <= b) ++k;
     ConstLevelDev& L = level_entry(a.lv, a.ent[k]);
     const int R = L.rows, C = L.cols;
-    const int t = b - a.blk[k];
-    const int tilesx = (C + kCombTile - 1) / kCombTile;
-    const int ty = t / tilesx, tx = t - ty * tilesx;
-    const int ti0 = ty * kCombTile, tj0 = tx * kCombTile;
-    const int ti1 = min(ti0 + kCombTile, R), tj1 = min(tj0 + kCombTile, C);
+    const int t = b - a.net.tblk[k];
+    const int tilesx = (C + TW - 1) / TW;
+    const int ti0 = (t / tilesx) * TH, tj0 = (t % tilesx) * TW;
+    const int ti1 = min(ti0 + TH, R), tj1 = min(tj0 + TW, C);
+    if (threadIdx.x == 0) nfb = 0;
+    net_tile(a.net.in, a.net.w, a.net.bias, a.net.segs.base[k], R, C, ti0, tj0, net_lds);
+    const float* out32 = reinterpret_cast<const float*>(net_lds);   // [3][TH][TW]
+    float* const X = reinterpret_cast<float*>(net_lds) + 3 * TH * TW;
+    float* const TM = X + 3 * kCombPlane;
     const int Ns = L.Ns;
     const int hal = 2 * Ns;
     const int gi0 = ti0 - hal, gj0 = tj0 - hal;
-    const int RW = kCombTile + 2 * hal;
+    const int RW = TW + 2 * hal;
     const int vi0 = max(gi0, 0), vi1 = min(ti1 + hal, R);
     const int vj0 = max(gj0, 0), vj1 = min(tj1 + hal, C);
-    if (threadIdx.x == 0) nfb = 0;
-    __syncthreads();
     const size_t P = (size_t)L.ltotal;
     float* lb = L.lbuf + L.lbase;
-    for (int q = threadIdx.x; q < (vi1 - vi0) * (vj1 - vj0); q += 256) {
+    for (int q = threadIdx.x; q < (vi1 - vi0) * (vj1 - vj0); q += NT) {
         const int i = vi0 + q / (vj1 - vj0);
         const int j = vj0 + q % (vj1 - vj0);
         const size_t p = (size_t)i * C + j;
         const int li = (i - gi0) * RW + (j - gj0);
-        for (int c = 0; c < 3; ++c) X[c][li] = lb[(kLearnXP + c) * P + p];
+        for (int c = 0; c < 3; ++c) X[c * kCombPlane + li] = lb[(kLearnXP + c) * P + p];
     }
-    // the network's output and the cost terms of this thread's tile pixels, loaded now so that
-    // their latency hides behind the smoothing (tile pixel q = threadIdx.x + 256 m)
-    constexpr int kPer = kCombTile * kCombTile / 256;
+    // the cost terms of this thread's tile pixels, loaded now so that their latency hides
+    // behind the averaging (tile pixel q = threadIdx.x + NT m)
+    constexpr int kPer = (TH * TW + NT - 1) / NT;
     const int tw = tj1 - tj0, npx = (ti1 - ti0) * tw;
     float pre[kPer][11];
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
-        const int q = threadIdx.x + 256 * m;
+        const int q = threadIdx.x + NT * m;
         const int qq = q < npx ? q : 0;
-        const size_t p = (size_t)(ti0 + qq / tw) * C + tj0 + qq % tw;
+        const int qi = qq / tw, qj = qq % tw;
+        const size_t p = (size_t)(ti0 + qi) * C + tj0 + qj;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pre[m][c] = lb[(kLearnOut + c) * P + p];
+        for (int c = 0; c < 3; ++c) pre[m][c] = out32[(c * TH + qi) * TW + qj];
 #pragma unroll
         for (int c = 0; c < 8; ++c) pre[m][3 + c] = lb[(kLearnFB + c) * P + p];
     }
@@ -1397,28 +1408,29 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
         const int oi0 = max(ti0 - rad, 0), oi1 = min(ti1 + rad, R);
         const int oj0 = max(tj0 - rad, 0), oj1 = min(tj1 + rad, C);
         const int ii0 = max(oi0 - 2, 0), ii1 = min(oi1 + 2, R);
-        for (int q = threadIdx.x; q < (ii1 - ii0) * (oj1 - oj0); q += 256) {
+        for (int q = threadIdx.x; q < (ii1 - ii0) * (oj1 - oj0); q += NT) {
             const int i = ii0 + q / (oj1 - oj0);
             const int j = oj0 + q % (oj1 - oj0);
             const int row = (i - gi0) * RW - gj0;
             for (int c = 0; c < 3; ++c) {
-                const float m2 = X[c][row + clampi(j - 2, 0, C - 1)];
-                const float m1 = X[c][row + clampi(j - 1, 0, C - 1)];
-                const float v0 = X[c][row + j];
-                const float p1 = X[c][row + clampi(j + 1, 0, C - 1)];
-                const float p2 = X[c][row + clampi(j + 2, 0, C - 1)];
-                TM[c][(i - gi0) * RW + (j - gj0)] = (((m2 + m1) + v0) + p1) + p2;
+                const float* Xc = X + c * kCombPlane;
+                const float m2 = Xc[row + clampi(j - 2, 0, C - 1)];
+                const float m1 = Xc[row + clampi(j - 1, 0, C - 1)];
+                const float v0 = Xc[row + j];
+                const float p1 = Xc[row + clampi(j + 1, 0, C - 1)];
+                const float p2 = Xc[row + clampi(j + 2, 0, C - 1)];
+                TM[c * kCombPlane + (i - gi0) * RW + (j - gj0)] = (((m2 + m1) + v0) + p1) + p2;
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < (oi1 - oi0) * (oj1 - oj0); q += 256) {
+        for (int q = threadIdx.x; q < (oi1 - oi0) * (oj1 - oj0); q += NT) {
             const int i = oi0 + q / (oj1 - oj0);
             const int j = oj0 + q % (oj1 - oj0);
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
                 for (int aa = -2; aa <= 2; ++aa)
-                    s += TM[c][(clampi(i + aa, 0, R - 1) - gi0) * RW + (j - gj0)];
-                X[c][(i - gi0) * RW + (j - gj0)] = s * 0.04f;
+                    s += TM[c * kCombPlane + (clampi(i + aa, 0, R - 1) - gi0) * RW + (j - gj0)];
+                X[c * kCombPlane + (i - gi0) * RW + (j - gj0)] = s * 0.04f;
             }
         }
         __syncthreads();
@@ -1428,7 +1440,7 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
     unsigned int myfb = 0;
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
-        const int q = threadIdx.x + 256 * m;
+        const int q = threadIdx.x + NT * m;
         if (q >= npx) continue;
         const int i = ti0 + q / tw;
         const int j = tj0 + q % tw;
@@ -1445,7 +1457,7 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
         myfb += fb ? 1u : 0u;
         const float dmu = pixel_dmu(L, i, j);
         for (int c = 0; c < 3; ++c) {
-            const float xs = X[c][li];
+            const float xs = X[c * kCombPlane + li];
             lb[(kLearnXS + c) * P + p] = xs;
             lb[(kLearnCorr + c) * P + p] = fb ? 0.0f : dmu * d[c];
             T* dst = (T*)(L.top ? L.w[q2][c] : L.dw[q2][c]);
@@ -1457,10 +1469,6 @@ __global__ void __launch_bounds__(256) k_combine(CombineArgs a) {
     if (threadIdx.x == 0 && nfb) atomicAdd(a.fallbacks, (unsigned long long)nfb);
 }
 
-// Learned-update training data of one stream's finest level, after its frame: 22 float32
-// planes [network inputs (9), prior x0 (3), least-squares solution x_ls (3), smoothed x_ls (3),
-// parent flow (3), dmu], flows in the level's field units (rad/frame; the increment at a level
-// with a parent).
 template <typename T>
 __global__ void __launch_bounds__(kElemBlock) k_learned_extract(ElemArgs a) {
     int k0, e, i, j;
@@ -1690,12 +1698,32 @@ hipError_t launch_learned_extract(int storage, const ElemArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int storage, const CombineArgs& a, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
+hipError_t launch_net_combine(int storage, const NetCombineArgs& args, hipStream_t s) {
+    using namespace nettile;
+    static std::atomic<uint64_t> prepared{0};   // devices the LDS limit was raised on
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(prepared.load() & bit)) {
+        for (const void* f : {(const void*)k_net_combine<float>, (const void*)k_net_combine<__half>}) {
+            e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNetLds);
+            if (e != hipSuccess) return e;
+        }
+        prepared.fetch_or(bit);
+    }
+    NetCombineArgs a = args;
+    int blocks = 0;
+    for (int k = 0; k < a.net.segs.n; ++k) {
+        a.net.tblk[k] = blocks;
+        blocks += ((a.net.segs.rows[k] + kNetTH - 1) / kNetTH) * ((a.net.segs.cols[k] + kNetTW - 1) / kNetTW);
+    }
+    a.net.tblk[a.net.segs.n] = blocks;
+    if (blocks == 0) return hipSuccess;
     if (storage == SF_FP16)
-        hipLaunchKernelGGL(k_combine<__half>, dim3(a.blk[a.n]), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_net_combine<__half>, dim3(blocks), dim3(kNetThreads), kNetLds, s, a);
     else
-        hipLaunchKernelGGL(k_combine<float>, dim3(a.blk[a.n]), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_net_combine<float>, dim3(blocks), dim3(kNetThreads), kNetLds, s, a);
     return hipGetLastError();
 }
 }  // namespace sflow
