@@ -138,7 +138,7 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
                 tuned=setting, graph=graph, overlap=overlap)
 
 
-def run_batched(n_streams, steps, warmup, storage=0, frames=6):
+def run_batched(n_streams, steps, warmup, storage=0, frames=20):
     """n_streams independent camera streams of mixed sizes advanced together: one pyramid
     launch and one reconstruction launch per two depths, the level-step launches and one
     output call per frame for all streams.  A step is one frame of every stream plus every
@@ -438,7 +438,7 @@ def _pinhole_dmu_t(seq, device):
     return d.to(torch.float32)
 
 
-def run_learned(n_streams, steps, warmup, frames=6, eval_frames=100, warm=10):
+def run_learned(n_streams, steps, warmup, frames=20, eval_frames=100, warm=10):
     """The learned update on n_streams 512 x 512 box sequences (3 levels, max flow 8 px;
     held-out seeds 20000 + i, not trained on), with the committed trained parameters and the
     fallback threshold chosen on validation seeds.  Throughput: plain and learned side by side
@@ -698,8 +698,11 @@ def copy_probe(mib: int, reps: int = 10, quiet: bool = False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    # the 512x512 frame takes about 43 us: 1000 timed frames after 200 untimed ones, so that the
+    # clocks and caches have settled before the timed region (100 frames after 10 measured a few
+    # per cent low in alternating runs)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="boxes512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and batched forms")
@@ -823,7 +826,8 @@ def main():
         print(f"[bench] fp16 storage: {forms['fp16_storage']['frames_per_s']:.1f} frames/s",
               flush=True)
         for st in (0, 1):
-            rb = run_batched(args.streams, max(5, args.steps // 5), 2, storage=st)
+            rb = run_batched(args.streams, max(5, args.steps // 5), max(2, args.warmup // 10),
+                             storage=st)
             forms[f"batched_{rb['storage']}"] = rb
             print(f"[bench] batched {rb['storage']}: {rb['aggregate_frames_per_s']:.1f} "
                   f"stream-frames/s ({rb['mpix_per_s']:.0f} Mpix/s)", flush=True)
@@ -859,7 +863,7 @@ def main():
               f"{rg['grid_equiangular_512']['frames_per_s']:.1f} frames/s; stereo: "
               f"{st['frames_per_s']:.1f} frames/s, true-flow EPE {st['gt_epe_px_stereo']:.4f} px "
               f"(depth sensor {st['gt_epe_px_depth']:.4f})", flush=True)
-        rl = run_learned(16, max(5, args.steps // 5), 2)
+        rl = run_learned(16, max(5, args.steps // 5), max(2, args.warmup // 10))
         forms["learned_16x512"] = rl
         print(f"[bench] learned 16x512: {rl['learned']['aggregate_frames_per_s']:.1f} "
               f"stream-frames/s (plain {rl['plain']['aggregate_frames_per_s']:.1f}); true-flow "
