@@ -86,6 +86,7 @@ def tune_levels(rows, cols, levels, max_flow, smooth):
 
 
 def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
+    import numpy as np
     import torch
     from paper_2406_18031_amd import sflow
     from synth.workloads import workload
@@ -113,6 +114,12 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
         f.push(Ys[k % F], Rs[k % F], seq.dt)
         sflow.sf_get_flow(f.ctx, sflow.SF_FLOW_W_RAD_S, out)
 
+    def restart():   # the next push is a first frame (the launch shape is kept)
+        sflow.sf_set_camera(f.ctx, cam.fx, cam.fy, cam.cx, cam.cy)
+
+    # every pass starts from a restarted state and runs warmup + steps frames, so that no pass
+    # carries the state further than the throughput pass (see finite_after)
+    restart()
     for k in range(warmup):
         step(k)
     torch.cuda.synchronize()
@@ -121,11 +128,15 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
         step(k)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    graph = graph_pass(f.ctx, step, steps, warmup)
-    overlap = overlap_pass(f.ctx, step, steps, warmup)
+    finite = bool(torch.isfinite(out).all())
+    graph = graph_pass(f.ctx, step, steps, warmup, restart)
+    overlap = overlap_pass(f.ctx, step, steps, warmup, restart)
 
     # kernel durations from HIP events on the context stream, over a second pass of the
     # same frames (events add host work, so the throughput pass above runs without them)
+    restart()
+    for k in range(warmup):
+        step(k)
     sflow.sf_set_timing(f.ctx, True)
     sflow.sf_kernel_times(f.ctx, reset=True)
     for k in range(warmup, warmup + steps):
@@ -135,10 +146,12 @@ def run_gpu(wl_name, steps, warmup, storage=0, autotune=False):
     final = f.flow(sflow.SF_FLOW_W_FRAME).cpu().numpy()
     f.close()
     return dict(seq=seq, wl=wl, elapsed=elapsed, kernel_ms=ms, kernel_n=n, final=final,
-                tuned=setting, graph=graph, overlap=overlap)
+                tuned=setting, graph=graph, overlap=overlap,
+                finite_after={"frames": warmup + steps, "timed_pass": finite,
+                              "timing_pass": bool(np.isfinite(final).all())})
 
 
-def run_batched(n_streams, steps, warmup, storage=0, frames=20):
+def run_batched(n_streams, steps, warmup, storage=0, frames=40):
     """n_streams independent camera streams of mixed sizes advanced together: one pyramid
     launch and one reconstruction launch per two depths, the level-step launches and one
     output call per frame for all streams.  A step is one frame of every stream plus every
@@ -183,21 +196,26 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=20):
     setting = tune.tune(b.ctx, lambda k: b.push([y[k % frames] for y in Ys],
                                                 [r[k % frames] for r in Rs], dts), lv)
 
-    for k in range(warmup):
+    def restart():   # every stream's next push is a first frame (the launch shape is kept)
+        sflow.sf_set_cameras(b.ctx, [sp["camera"] for sp in specs])
+
+    def finite():
+        return all(bool(torch.isfinite(o).all()) for o in outs)
+
+    warm = max(2, min(warmup, frames // 8))
+    elapsed, steps, fin_timed = segmented(step, restart, finite, steps, frames, warm)
+    graph = graph_pass(b.ctx, step, frames - warm, warm, restart)
+    restart()
+    for k in range(warm):
         step(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(warmup, warmup + steps):
-        step(k)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    graph = graph_pass(b.ctx, step, steps, warmup)
     sflow.sf_set_timing(b.ctx, True)
     sflow.sf_kernel_times(b.ctx, reset=True)
-    for k in range(warmup, warmup + steps):
+    for k in range(warm, frames):
         step(k)
     ms, n = sflow.sf_kernel_times(b.ctx, reset=True)
+    fin_timing = finite()
     b.close()
+    kt = frames - warm   # frames of the kernel-timing pass
     px = sum(sp["rows"] * sp["cols"] for sp in specs)
     step_bytes = step_flops = 0
     for sp in specs:
@@ -205,7 +223,7 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=20):
             npx = L["rows"] * L["cols"]
             step_bytes += npx * step_bytes_per_px(L["top"], 2 if storage == 1 else 4)
             step_flops += npx * step_flops_per_px(L["top"], L["N"], L["Ns"])
-    step_s = ms[1] / max(1, steps) * 1e-3          # level-step time per frame (all passes)
+    step_s = ms[1] / kt * 1e-3          # level-step time per frame (all passes)
     sizes = {}
     for sp in specs:
         sizes[sp["rows"]] = sizes.get(sp["rows"], 0) + 1
@@ -215,23 +233,51 @@ def run_batched(n_streams, steps, warmup, storage=0, frames=20):
         "aggregate_frames_per_s": len(specs) * steps / elapsed,
         "batch_steps_per_s": steps / elapsed,
         "mpix_per_s": px * steps / elapsed / 2 ** 20,
-        "kernel_us_per_frame": {k: v / max(1, steps) * 1e3 for k, v in
+        "kernel_us_per_frame": {k: v / kt * 1e3 for k, v in
                                 zip(("pyramid", "level_step", "reconstruct"), ms)},
         "level_step_tflops": step_flops / step_s / 1e12,
         "level_step_hbm_gbs": step_bytes / step_s / 1e9,
         "tuned": {"pass_steps": setting["pass_steps"], "tiles": setting["tiles"]},
         "frame_graph": graph,
+        "timing": f"{steps} frames in segments of frames {warm}-{frames - 1} after a restart "
+                  f"({frames} rendered frames per stream, cycled)",
+        "finite_after": {"frames": frames, "timed_pass": fin_timed, "timing_pass": fin_timing},
     }
 
 
-def overlap_pass(ctx, step, steps, warmup):
+def segmented(step, restart, finite, n_timed, cycle, warm):
+    """Throughput of a form whose inputs repeat every `cycle` frames, timed in segments: each
+    segment restarts the state, runs `warm` untimed frames and times frames warm..cycle-1, so
+    that no timed frame follows a jump back to the cycle's first frame and no state is older
+    than one cycle (the method's state grows without bound after O(100-1000) frames of cycled
+    inputs, in the FP64 oracle too).  Returns (elapsed seconds, timed frames, state finite at
+    the end of every segment)."""
+    import torch
+    el, done, fin = 0.0, 0, True
+    while done < n_timed:
+        restart()
+        for k in range(warm):
+            step(k)
+        m = min(cycle - warm, n_timed - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(warm, warm + m):
+            step(k)
+        torch.cuda.synchronize()
+        el += time.perf_counter() - t0
+        done += m
+        fin = fin and finite()
+    return el, done, fin
+
+
+def overlap_pass(ctx, step, steps, warmup, restart):
     """The same loop with the frames declared as produced on a stream of their own
     (sf_set_input_stream; they are resident in HBM already, so that stream holds no work): each
     frame's pyramid then runs on the library's pyramid stream beside the previous frame's level
-    step.  Throughput over the same frames, and the final flow for a bitwise check against the
-    default mode."""
+    step.  Throughput over the same frames from a restarted state."""
     import torch
     from paper_2406_18031_amd import sflow
+    restart()
     s_in = torch.cuda.Stream()
     sflow.sf_set_input_stream(ctx, s_in)
     for k in range(warmup):
@@ -246,14 +292,16 @@ def overlap_pass(ctx, step, steps, warmup):
     return {"steps_per_s": steps / el, "ms_per_step": el / steps * 1e3}
 
 
-def graph_pass(ctx, step, steps, warmup):
+def graph_pass(ctx, step, steps, warmup, restart):
     """The same loop with the frame's launches replayed from a HIP graph (sf_set_graph):
     throughput, and the host time per step with and without the graph (the loop's wall time
-    up to its last submission, before waiting for the device)."""
+    up to its last submission, before waiting for the device); each loop from a restarted
+    state."""
     import torch
     from paper_2406_18031_amd import sflow
     out = {}
     for on in (False, True):
+        restart()
         sflow.sf_set_graph(ctx, on)
         for k in range(warmup):
             step(k)
@@ -320,14 +368,16 @@ def run_inertial(steps, warmup):
                     f.push(Ys[k % F], Rs[k % F], seq.dt, omega=m[0], omega_dot=m[1], acc=m[2])
                     sflow.sf_get_flow(f.ctx, sflow.SF_FLOW_W_RAD_S, out_t)
 
-                for k in range(warmup):
-                    step(k)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for k in range(warmup, warmup + steps):
-                    step(k)
-                torch.cuda.synchronize()
-                out["frames_per_s"] = steps / (time.perf_counter() - t0)
+                def restart():
+                    sflow.sf_set_camera(f.ctx, cam.fx, cam.fy, cam.cx, cam.cy)
+
+                def finite():
+                    return bool(torch.isfinite(out_t).all())
+
+                el, nt, fin = segmented(step, restart, finite, steps, F, 10)
+                out["frames_per_s"] = nt / el
+                out["timing"] = (f"{nt} frames in segments of frames 10-{F - 1} after a restart")
+                out["finite_after"] = {"frames": F, "timed_pass": fin}
             f.close()
         row["gt_epe_inertial_over_plain"] = row["gt_epe_px_inertial"] / row["gt_epe_px_plain"]
         out[name] = row
@@ -350,7 +400,8 @@ def run_grid_stereo(steps, warmup, frames=40, warm=10):
     from synth.scenes import box_sequence, equiangular_rays
     out = {}
     # grid + mapping
-    src = box_sequence(640, 640, 8, seed=2, max_flow_px=10.0, device="cuda")
+    GF = 100
+    src = box_sequence(640, 640, GF, seed=2, max_flow_px=10.0, device="cuda")
     c = src.camera
     Ys, Rs = render_frames(src, "cuda")
     eta = equiangular_rays(512, 512, 90.0)
@@ -361,19 +412,19 @@ def run_grid_stereo(steps, warmup, frames=40, warm=10):
     o = torch.empty((3, 512, 512), dtype=torch.float32, device="cuda")
 
     def gstep(k):
-        g.map(Ys[k % 8], Rs[k % 8], Yg, Rg)
+        g.map(Ys[k % GF], Rs[k % GF], Yg, Rg)
         g.push(Yg, Rg, src.dt)
         sflow.sf_get_flow(g.ctx, sflow.SF_FLOW_W_RAD_S, o)
 
-    for k in range(warmup):
-        gstep(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(warmup, warmup + steps):
-        gstep(k)
-    torch.cuda.synchronize()
+    def grestart():
+        sflow.sf_set_camera(g.ctx, 256.0, 256.0, 255.5, 255.5, eta)
+        g.set_source_camera(c.fx, c.fy, c.cx, c.cy, 640, 640)
+
+    el, nt, fin = segmented(gstep, grestart, lambda: bool(torch.isfinite(o).all()), steps, GF, 10)
     out["grid_equiangular_512"] = {
-        "frames_per_s": steps / (time.perf_counter() - t0),
+        "frames_per_s": nt / el,
+        "timing": f"{nt} frames in segments of frames 10-{GF - 1} after a restart",
+        "finite_after": {"frames": GF, "timed_pass": fin},
         "workload": "512x512 equiangular grid of 90 degrees, frames mapped from a 640x640 "
                     "pinhole camera each step (map + push + read)"}
     g.close()
@@ -418,6 +469,8 @@ def run_grid_stereo(steps, warmup, frames=40, warm=10):
                 sstep(k)
             torch.cuda.synchronize()
             row["frames_per_s"] = steps / (time.perf_counter() - t0)
+            row["finite_after"] = {"frames": frames + warmup + steps,
+                                   "timed_pass": bool(torch.isfinite(o).all())}
         f.close()
     row["workload"] = (f"boxes512 scene seen by a rectified stereo pair (baseline {b} m, "
                        f"disparities up to {dmax} px); accuracy over frames {warm}-{frames - 1}")
@@ -438,7 +491,7 @@ def _pinhole_dmu_t(seq, device):
     return d.to(torch.float32)
 
 
-def run_learned(n_streams, steps, warmup, frames=20, eval_frames=100, warm=10):
+def run_learned(n_streams, steps, warmup, frames=40, eval_frames=100, warm=10):
     """The learned update on n_streams 512 x 512 box sequences (3 levels, max flow 8 px;
     held-out seeds 20000 + i, not trained on), with the committed trained parameters and the
     fallback threshold chosen on validation seeds.  Throughput: plain and learned side by side
@@ -480,16 +533,19 @@ def run_learned(n_streams, steps, warmup, frames=20, eval_frames=100, warm=10):
             b.push([y[k % frames] for y in Ys], [r[k % frames] for r in Rs], dts)
             sflow.sf_get_flows(b.ctx, sflow.SF_FLOW_W_RAD_S, outs)
 
-        for k in range(warmup):
-            step(k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(warmup, warmup + steps):
-            step(k)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[name] = {"aggregate_frames_per_s": n_streams * steps / el,
-                     "ms_per_batch_frame": el / steps * 1e3}
+        def restart(b=b):
+            sflow.sf_set_cameras(b.ctx, [sp["camera"] for sp in specs])
+
+        def finite(outs=outs):
+            return all(bool(torch.isfinite(o).all()) for o in outs)
+
+        w0 = max(2, min(warmup, frames // 8))
+        el, nt, fin = segmented(step, restart, finite, steps, frames, w0)
+        out[name] = {"aggregate_frames_per_s": n_streams * nt / el,
+                     "ms_per_batch_frame": el / nt * 1e3,
+                     "timing": f"{nt} frames in segments of frames {w0}-{frames - 1} after a "
+                               f"restart ({frames} rendered frames per stream, cycled)",
+                     "finite_after": {"frames": frames, "timed_pass": fin}}
         b.close()
     # accuracy against the true flow, both forms on the same rendered frames
     bp = sflow.Batch(specs)
@@ -527,7 +583,7 @@ def run_learned(n_streams, steps, warmup, frames=20, eval_frames=100, warm=10):
     return out
 
 
-def run_sweep(steps, warmup, frames=8):
+def run_sweep(steps, warmup, frames=100):
     """The paper's runtime tables' shapes (512^2 one level; 512^2 and 1024^2 two levels;
     maximum flow 1/2/4/8 px; smoothing 2 / [2, 4]) on seeded box scenes: frames/s of the push
     plus output read, and the level step's HIP-event duration per frame."""
@@ -549,17 +605,18 @@ def run_sweep(steps, warmup, frames=8):
                 f.push(Ys[k % frames], Rs[k % frames], seq.dt)
                 sflow.sf_get_flow(f.ctx, sflow.SF_FLOW_W_RAD_S, out)
 
-            for k in range(warmup):
+            def restart():
+                sflow.sf_set_camera(f.ctx, c.fx, c.fy, c.cx, c.cy)
+
+            w0 = 10
+            el, nt, fin = segmented(step, restart, lambda: bool(torch.isfinite(out).all()),
+                                    steps, frames, w0)
+            restart()
+            for k in range(w0):
                 step(k)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for k in range(warmup, warmup + steps):
-                step(k)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
             sflow.sf_set_timing(f.ctx, True)
             sflow.sf_kernel_times(f.ctx, reset=True)
-            for k in range(warmup, warmup + steps):
+            for k in range(w0, frames):
                 step(k)
             ms, n = sflow.sf_kernel_times(f.ctx, reset=True)
             f.close()
@@ -568,9 +625,10 @@ def run_sweep(steps, warmup, frames=8):
                 "table": t["table"], "size": t["size"], "levels": t["levels"],
                 "smooth": t["smooth"], "max_flow_px": mf,
                 "N": [L["N"] for L in levels],
-                "frames_per_s": steps / el, "ms_per_frame": el / steps * 1e3,
-                "mpix_per_s": t["size"] ** 2 * steps / el / 2 ** 20,
-                "level_step_us_per_frame": ms[1] / steps * 1e3,
+                "frames_per_s": nt / el, "ms_per_frame": el / nt * 1e3,
+                "mpix_per_s": t["size"] ** 2 * nt / el / 2 ** 20,
+                "level_step_us_per_frame": ms[1] / (frames - w0) * 1e3,
+                "finite_after": {"frames": frames, "timed_pass": fin},
             })
             print(f"[sweep] {t['table']} {t['size']}^2 H={t['levels']} flow {mf:g}: "
                   f"{rows[-1]['frames_per_s']:.0f} frames/s", flush=True)
@@ -801,6 +859,9 @@ def main():
             zip(("pyramid", "level_step", "reconstruct"), r["kernel_ms"], r["kernel_n"])},
         "paper_context": {"hz": 594.7, "workload": "512x512, 2 levels, max flow 8 px, GTX-780",
                           "source": "Table runtime_pyramid_2"},
+        # the method's state grows without bound after O(1000) frames of these cycled inputs
+        # (the FP64 oracle too); every pass restarts it and reports that it stayed finite
+        "finite_after": r["finite_after"],
         "frame_graph": r["graph"],
         # the same frames declared as produced on a stream of their own (sf_set_input_stream):
         # the pyramid runs beside the previous frame's level step
@@ -821,7 +882,8 @@ def main():
             "level_step_hbm_gbs": sum(L["rows"] * L["cols"] * step_bytes_per_px(L["top"], 2)
                                       for L in levels) / (ms16 * 1e-3) / 1e9,
             "epe_vs_fp32_storage_px": {"mean": float(d.mean()), "max": float(d.max()),
-                                       "after_frames": args.warmup + 2 * args.steps},
+                                       "after_frames": args.warmup + args.steps},
+            "finite_after": r16["finite_after"],
         }
         print(f"[bench] fp16 storage: {forms['fp16_storage']['frames_per_s']:.1f} frames/s",
               flush=True)
@@ -841,6 +903,7 @@ def main():
             "frames_per_s": max(10, args.steps // 2) / rd["elapsed"],
             "level_step_us_per_frame": msd * launches * 1e3,
             "level_step_launches_per_frame": launches,
+            "finite_after": rd["finite_after"],
             "level_step_hbm_gbs": sum(L["rows"] * L["cols"] * step_bytes_per_px(L["top"], 2)
                                       for L in ld) / (msd * launches * 1e-3) / 1e9,
             "workload": "2048x1024, 4 levels, max flow 16 px (N=16/8/4/2), driving scene, "
