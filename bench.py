@@ -524,7 +524,7 @@ def run_learned(n_streams, steps, warmup, frames=40, eval_frames=100, warm=10):
     params, threshold = learned.load_trained()
     seqs, specs, Ys, Rs = [], [], [], []
     for i in range(n_streams):
-        seq = box_sequence(512, 512, eval_frames, seed=20000 + i, dt=1.0 / 300.0,
+        seq = box_sequence(512, 512, max(eval_frames, frames), seed=20000 + i, dt=1.0 / 300.0,
                            max_flow_px=8.0, device="cuda")
         c = seq.camera
         seqs.append(seq)

@@ -56,6 +56,13 @@ static_assert(3 * kNetTH * kNetTW * 4 <= kNetRowsX * kNetPitch * 32, "output sta
 
 constexpr int kNetLayers = 4;
 
+// LDS slot of channel quad q (8 bytes) of the pixel in column c of an activation row.  A
+// B-operand read or an output write touches one quad of 16 consecutive pixels (32 bytes
+// apart), which would put them on 8 of the 32 four-byte banks (4-way conflicts); XOR-ing the
+// quad with bits 2-3 of the column gives the four pixels of equal column mod 4 four different
+// slots, so any 16 consecutive pixels cover every bank once.
+__device__ __forceinline__ int qslot(int c, int q) { return q ^ ((c >> 2) & 3); }
+
 // The tile of the image whose pixels start at in + 16 base (BF16 NHWC 16, rows x cols) with
 // its top-left output pixel at (ty0, tx0); w: BF16 [4][9][16 out][16 in], bias: FP32 [4][16].
 // Leaves the three FP32 output channels of the tile in LDS at lds, as [3][kNetTH][kNetTW], and
@@ -84,11 +91,16 @@ __device__ __forceinline__ void net_tile(const uint16_t* in, const uint16_t* wts
             const size_t off = inb[m] ? ((size_t)base + (size_t)yy * cols + xx) * 16 + half * 8 : 0;
             vv[m] = *(const uint4*)(in + off);
         }
+        // quads 2 half, 2 half + 1 of a pixel go to slots qslot(): the 16-byte chunk moves to
+        // position half ^ (s >> 1) of the pixel, its 8-byte halves swapped when s is odd
         uint4* X4 = reinterpret_cast<uint4*>(X);
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
             const int q = threadIdx.x + kNetThreads * m;
-            if (q < NQ) X4[q] = inb[m] ? vv[m] : make_uint4(0u, 0u, 0u, 0u);
+            const int sw = ((q >> 1) % kNetPitch >> 2) & 3;
+            uint4 v = inb[m] ? vv[m] : make_uint4(0u, 0u, 0u, 0u);
+            if (sw & 1) v = make_uint4(v.z, v.w, v.x, v.y);
+            if (q < NQ) X4[q ^ (sw >> 1)] = v;
         }
     }
     float* const out32 = reinterpret_cast<float*>(X);         // [3][TH][TW], after layer 2
@@ -114,7 +126,8 @@ __device__ __forceinline__ void net_tile(const uint16_t* in, const uint16_t* wts
         auto load_row = [&](s4 (&g)[3], int row) {
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx)
-                g[dx] = unpack4(src[((size_t)row * kNetPitch + x0 + col + dx) * 4 + quad]);
+                g[dx] = unpack4(src[((size_t)row * kNetPitch + x0 + col + dx) * 4 +
+                                    qslot(x0 + col + dx, quad)]);
         };
         // output row r: D[4 quad + k][col] is channel 4 quad + k of pixel px
         auto store_row = [&](int r, const f4& acc) {
@@ -124,7 +137,7 @@ __device__ __forceinline__ void net_tile(const uint16_t* in, const uint16_t* wts
                 uint16_t h[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) h[k] = in ? f2bf(fmaxf(acc[k] + bias[k], 0.0f)) : (uint16_t)0;
-                dst[((size_t)r * kNetPitch + px) * 4 + quad] =
+                dst[((size_t)r * kNetPitch + px) * 4 + qslot(px, quad)] =
                     make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
             } else if (quad == 0 && px < kNetTW) {
 #pragma unroll
