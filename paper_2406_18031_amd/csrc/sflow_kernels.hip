@@ -1379,9 +1379,13 @@ __global__ void __launch_bounds__(nettile::kNetThreads) k_net_combine(NetCombine
     const int vj0 = max(gj0, 0), vj1 = min(tj1 + hal, C);
     const size_t P = (size_t)L.ltotal;
     float* lb = L.lbuf + L.lbase;
-    for (int q = threadIdx.x; q < (vi1 - vi0) * (vj1 - vj0); q += NT) {
-        const int i = vi0 + q / (vj1 - vj0);
-        const int j = vj0 + q % (vj1 - vj0);
+    // the averaging region is at most TW + 16 <= 64 columns wide (N_s <= 4): a lane per column,
+    // the waves take its rows in turn (no per-element division)
+    static_assert(TW + 16 <= 64, "one lane per column of the averaging region");
+    constexpr int NWV = NT / 64;
+    const int lc = threadIdx.x & 63, lw = threadIdx.x >> 6;
+    for (int i = vi0 + lw; vj0 + lc < vj1 && i < vi1; i += NWV) {
+        const int j = vj0 + lc;
         const size_t p = (size_t)i * C + j;
         const int li = (i - gi0) * RW + (j - gj0);
         for (int c = 0; c < 3; ++c) X[c * kCombPlane + li] = lb[(kLearnXP + c) * P + p];
@@ -1408,9 +1412,8 @@ __global__ void __launch_bounds__(nettile::kNetThreads) k_net_combine(NetCombine
         const int oi0 = max(ti0 - rad, 0), oi1 = min(ti1 + rad, R);
         const int oj0 = max(tj0 - rad, 0), oj1 = min(tj1 + rad, C);
         const int ii0 = max(oi0 - 2, 0), ii1 = min(oi1 + 2, R);
-        for (int q = threadIdx.x; q < (ii1 - ii0) * (oj1 - oj0); q += NT) {
-            const int i = ii0 + q / (oj1 - oj0);
-            const int j = oj0 + q % (oj1 - oj0);
+        for (int i = ii0 + lw; oj0 + lc < oj1 && i < ii1; i += NWV) {
+            const int j = oj0 + lc;
             const int row = (i - gi0) * RW - gj0;
             for (int c = 0; c < 3; ++c) {
                 const float* Xc = X + c * kCombPlane;
@@ -1423,9 +1426,8 @@ __global__ void __launch_bounds__(nettile::kNetThreads) k_net_combine(NetCombine
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < (oi1 - oi0) * (oj1 - oj0); q += NT) {
-            const int i = oi0 + q / (oj1 - oj0);
-            const int j = oj0 + q % (oj1 - oj0);
+        for (int i = oi0 + lw; oj0 + lc < oj1 && i < oi1; i += NWV) {
+            const int j = oj0 + lc;
             for (int c = 0; c < 3; ++c) {
                 float s = 0.0f;
                 for (int aa = -2; aa <= 2; ++aa)

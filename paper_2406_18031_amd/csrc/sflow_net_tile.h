@@ -18,14 +18,9 @@ __device__ __forceinline__ float bf2f(uint16_t v) {
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (v_cvt_pk_bf16_f32)
     return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
-__device__ __forceinline__ s4 unpack4(uint2 v) {
-    s4 r;
-    r[0] = (short)(v.x & 0xffff);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xffff);
-    r[3] = (short)(v.y >> 16);
-    return r;
-}
+// four BF16 values packed little-endian in two dwords, as the MFMA operand (element k = bits
+// 16 k .. 16 k + 15): the same registers, no instruction
+__device__ __forceinline__ s4 unpack4(uint2 v) { return __builtin_bit_cast(s4, v); }
 
 // The four layers (inference: no layer input is kept) on one tile.  A block of 12 waves
 // computes a kNetTH x kNetTW tile of one image's output (two blocks fit a CU's LDS).  It
