@@ -53,7 +53,7 @@ typedef enum {
     SF_ERR_OOM = -3,         /* device allocation failed                                   */
     SF_ERR_HIP = -4,         /* a HIP runtime call failed; the context is unusable          */
     SF_ERR_UNSUPPORTED = -5, /* valid request this build does not implement                */
-    SF_ERR_NUMERIC = -6      /* reserved                                                   */
+    SF_ERR_NUMERIC = -6      /* a stored flow value was not finite (sf_check_state)        */
 } sf_status;
 
 /* element type of images and stored state */
@@ -171,6 +171,19 @@ sf_status sf_get_flow(sf_ctx ctx, int32_t kind, void* out);
 
 /* Bytes of the state blob of sf_get_state / sf_set_state. */
 sf_status sf_state_size(sf_ctx ctx, size_t* bytes);
+
+/* Watchdog of the state.  Every launch that stores a level's new flow (w at the top level,
+ * dw below; Sections "State update" and "Numerical prediction") tests each stored value and sets
+ * bit s of a device word when a value of stream s is NaN, infinite or, with FP16 storage,
+ * beyond the FP16 range; this costs no synchronisation and a ballot per wave.  sf_check_state
+ * synchronises the context stream, writes the word to *streams (bit s = stream s), clears it
+ * and returns SF_ERR_NUMERIC (with the streams in sf_last_error) if it was set, else SF_OK.
+ * The word is also cleared when the cameras are set (the state restarts).  Why: the
+ * prediction's source term f<eta, w> lets the flow's normal component grow without bound where
+ * the update observes it only weakly, so a long run of a scene can end in non-finite flow;
+ * inputs with infinite values do the same.  A caller checks every so many frames and restarts
+ * the stream (sf_set_camera) or restores a saved state (sf_set_state) when it fails. */
+sf_status sf_check_state(sf_ctx ctx, uint64_t* streams);
 
 /* Copy the whole filter state to / from HOST memory (synchronises the stream).  The blob is
  * a 32-byte header {uint32 magic 'SFST', uint32 version 1, int32 levels, int32 initialised,

@@ -96,6 +96,7 @@ struct sf_ctx_s {
     float* cnn_bias = nullptr;           // [4][16]
     float* params_dev = nullptr;         // FP32 master weights
     unsigned long long* fallbacks = nullptr;
+    unsigned long long* numeric = nullptr;    // watchdog word (LevelDev::numeric), in the arena
     int64_t learned_pixels = 0;
     // Frame graphs (sf_set_graph): a frame's launches after the first frame, captured once per
     // state parity and per form of the prediction (plain / inertial), replayed with the
@@ -460,6 +461,7 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         }
     }
     total += align + sizeof(LevelDev) * (ctx->lv.size() + kLevelPad);   // zeroed padding
+    total += 256;                                                          // watchdog word
     hipError_t e = dev_malloc((void**)&ctx->arena, total);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -484,6 +486,8 @@ sf_status sf_create_batch(const sf_config* cfgs, int32_t n, void* hip_stream, sf
         }
     }
     ctx->lv_dev = (LevelDev*)take(sizeof(LevelDev) * (ctx->lv.size() + kLevelPad));
+    ctx->numeric = (unsigned long long*)take(256);
+    for (auto& L : ctx->lv) L.numeric = ctx->numeric;
     if (cf[0].update == SF_UPDATE_LEARNED) {
         ctx->learned = true;
         CnnSegs& sg = ctx->segs;
@@ -801,6 +805,7 @@ sf_status sf_set_cameras(sf_ctx c, const sf_camera* cams) {
     }
     if (old_geo) (void)hipFree(old_geo);   // upload_levels synchronised the stream
     c->recon_pending = false;   // the state restarts
+    HIP_TRY(c, hipMemsetAsync(c->numeric, 0, sizeof *c->numeric, c->stream));
     c->camera = true;
     c->frames = 0;
     c->parity = 0;
@@ -1028,6 +1033,24 @@ sf_status sf_set_learned(sf_ctx c, const float* params, size_t n, float threshol
     c->threshold = threshold;
     c->weights = true;
     return SF_OK;
+}
+
+sf_status sf_check_state(sf_ctx c, uint64_t* streams) {
+    sf_status st = check_alive(c);
+    if (st != SF_OK) return st;
+    if (!streams) return fail(c, SF_ERR_INVALID_ARG, "NULL output");
+    unsigned long long v = 0;
+    HIP_TRY(c, hipMemcpyAsync(&v, c->numeric, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *streams = (uint64_t)v;
+    if (!v) return SF_OK;
+    HIP_TRY(c, hipMemsetAsync(c->numeric, 0, sizeof v, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int first = 0;
+    while (!((v >> first) & 1ull)) ++first;
+    return fail(c, SF_ERR_NUMERIC,
+                "a stored flow value was not finite (streams mask 0x%llx, first %d) since the "
+                "last check", v, first);
 }
 
 sf_status sf_learned_stats(sf_ctx c, int64_t* fallbacks, int64_t* pixels, int32_t reset) {

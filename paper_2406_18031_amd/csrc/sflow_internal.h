@@ -83,6 +83,10 @@ struct LevelDev {
     int pass_last;                   // 1: runs the update, smoothing and state store
     float* mid_in[8];                // FP32 fields after the previous pass (pitch = pitch)
     float* mid_out[8];               // FP32 fields after this pass
+    // the context's watchdog word: the kernels that store a level's new flow set bit `stream`
+    // when a value is not finite (or, in FP16 storage, beyond its range); sf_check_state reads
+    // and clears it
+    unsigned long long* numeric;
 };
 
 // Per-frame arguments: the finest-level measurements of every stream (caller's device

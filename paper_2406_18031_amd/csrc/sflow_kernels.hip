@@ -213,6 +213,19 @@ __device__ __forceinline__ void row_geo(ConstLevelDev& L, int i, float x, float 
     B = fxrn * (r2 * rinv) * inv;
 }
 
+// Largest magnitude a stored flow value may have: beyond it (or NaN) the store is flagged.
+template <typename T> __device__ __forceinline__ float stored_max();
+template <> __device__ __forceinline__ float stored_max<float>() { return 3.4028234663852886e38f; }
+template <> __device__ __forceinline__ float stored_max<__half>() { return 65504.0f; }
+
+// Sets the stream's bit of the watchdog word if any lane of the wave stored a flagged value:
+// one atomic from the wave's first flagged lane (called by every lane of the wave).
+__device__ __forceinline__ void flag_nonfinite(bool bad, int lane, ConstLevelDev& L) {
+    const unsigned long long m = __ballot(bad);
+    if (m != 0ull && lane == __ffsll((long long)m) - 1)
+        atomicOr(L.numeric, 1ull << L.stream);
+}
+
 constexpr int kNW = kBlock / 64;        // waves per block
 constexpr int kRPW = kRegion / kNW;     // region rows per wave
 
@@ -885,6 +898,7 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
     {
         const float os = flow_out_scale<T>(L);
         const bool tcol = j >= tj0 && j < tj1 && lane < RW;
+        bool bad = false;
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
             const int i = wi0 + r;
@@ -893,9 +907,12 @@ __device__ __forceinline__ void level_tile(const StepArgs& a, ConstLevelDev& L, 
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 T* dst = (T*)(TOP ? L.w[1 - par][k] : L.dw[1 - par][k]);
-                stv(dst, go, F[r][KX + k] * os);
+                const float v = F[r][KX + k] * os;
+                bad = bad || !(fabsf(v) <= stored_max<T>());
+                stv(dst, go, v);
             }
         }
+        flag_nonfinite(bad, lane, L);
     }
 }
 
@@ -1440,6 +1457,7 @@ __global__ void __launch_bounds__(nettile::kNetThreads) k_net_combine(NetCombine
     const float os = flow_out_scale<T>(L);
     const int q2 = a.parity;
     unsigned int myfb = 0;
+    bool bad = false;
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
         const int q = threadIdx.x + NT * m;
@@ -1463,9 +1481,12 @@ __global__ void __launch_bounds__(nettile::kNetThreads) k_net_combine(NetCombine
             lb[(kLearnXS + c) * P + p] = xs;
             lb[(kLearnCorr + c) * P + p] = fb ? 0.0f : dmu * d[c];
             T* dst = (T*)(L.top ? L.w[q2][c] : L.dw[q2][c]);
-            stv(dst, go, xs * os);
+            const float v = xs * os;
+            bad = bad || !(fabsf(v) <= stored_max<T>());
+            stv(dst, go, v);
         }
     }
+    flag_nonfinite(bad, threadIdx.x & 63, L);
     if (myfb) atomicAdd(&nfb, myfb);
     __syncthreads();
     if (threadIdx.x == 0 && nfb) atomicAdd(a.fallbacks, (unsigned long long)nfb);

@@ -117,6 +117,7 @@ def _load():
         "sf_learned_stats": (st, [vp, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
         "sf_get_update_inputs": (st, [vp, ctypes.c_int32, vp]),
+        "sf_check_state": (st, [vp, ctypes.POINTER(ctypes.c_uint64)]),
         "sf_net_create": (st, [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.c_int32, vp, ctypes.POINTER(vp)]),
         "sf_net_set_params": (st, [vp, vp, ctypes.c_size_t]),
@@ -146,7 +147,8 @@ EXPORTED = ("sf_create", "sf_set_camera", "sf_push_frame", "sf_get_flow", "sf_st
             "sf_net_forward", "sf_net_train_step", "sf_net_set_loss", "sf_net_destroy",
             "sf_net_last_error", "sf_net_forward_noalloc", "sf_push_frame_ex",
             "sf_push_frames_ex", "sf_set_graph", "sf_copy_probe", "sf_set_source_camera",
-            "sf_map_frame", "sf_set_stereo", "sf_stereo_depth", "sf_set_input_stream")
+            "sf_map_frame", "sf_set_stereo", "sf_stereo_depth", "sf_set_input_stream",
+            "sf_check_state")
 
 
 def _check(status: int, ctx) -> None:
@@ -394,6 +396,16 @@ def sf_set_learned(ctx: int, params, threshold: float) -> None:
     _check(lib.sf_set_learned(ctx, a.ctypes.data, a.size, threshold), ctx)
 
 
+def sf_check_state(ctx: int) -> int:
+    """Mask of the streams whose stored flow was not finite since the last check (0: none);
+    clears it.  Raises only for errors other than SF_ERR_NUMERIC."""
+    m = ctypes.c_uint64()
+    status = lib.sf_check_state(ctx, ctypes.byref(m))
+    if status != SF_ERR_NUMERIC:
+        _check(status, ctx)
+    return m.value
+
+
 def sf_learned_stats(ctx: int, reset: bool = False):
     fb, px = ctypes.c_int64(), ctypes.c_int64()
     _check(lib.sf_learned_stats(ctx, ctypes.byref(fb), ctypes.byref(px), int(reset)), ctx)
@@ -587,6 +599,10 @@ class Filter:
     def learned_stats(self, reset=False):
         return sf_learned_stats(self.ctx, reset)
 
+    def check_state(self):
+        """True if every stored flow value was finite since the last check (clears the flag)."""
+        return sf_check_state(self.ctx) == 0
+
     def close(self):
         if self.ctx:
             sf_destroy(self.ctx)
@@ -699,6 +715,11 @@ class Batch:
 
     def learned_stats(self, reset=False):
         return sf_learned_stats(self.ctx, reset)
+
+    def check_state(self):
+        """Streams whose stored flow was not finite since the last check (clears the flag)."""
+        m = sf_check_state(self.ctx)
+        return [s for s in range(len(self.specs)) if (m >> s) & 1]
 
     def close(self):
         if self.ctx:
