@@ -18,6 +18,12 @@ __device__ __forceinline__ float bf2f(uint16_t v) {
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (v_cvt_pk_bf16_f32)
     return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+// two values rounded to BF16 (nearest even) in one instruction, a in the low half
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2){a, b}, bf2));
+}
 // four BF16 values packed little-endian in two dwords, as the MFMA operand (element k = bits
 // 16 k .. 16 k + 15): the same registers, no instruction
 __device__ __forceinline__ s4 unpack4(uint2 v) { return __builtin_bit_cast(s4, v); }
@@ -129,11 +135,10 @@ __device__ __forceinline__ void net_tile(const uint16_t* in, const uint16_t* wts
             if (l < kNetLayers - 1) {
                 const int gy = ty0 - halo + r;
                 const bool in = col_in && gy >= 0 && gy < rows;
-                uint16_t h[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) h[k] = in ? f2bf(fmaxf(acc[k] + bias[k], 0.0f)) : (uint16_t)0;
+                const uint32_t lo = f2bf2(fmaxf(acc[0] + bias[0], 0.0f), fmaxf(acc[1] + bias[1], 0.0f));
+                const uint32_t hi = f2bf2(fmaxf(acc[2] + bias[2], 0.0f), fmaxf(acc[3] + bias[3], 0.0f));
                 dst[((size_t)r * kNetPitch + px) * 4 + qslot(px, quad)] =
-                    make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+                    make_uint2(in ? lo : 0u, in ? hi : 0u);
             } else if (quad == 0 && px < kNetTW) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) out32[(k * kNetTH + r) * kNetTW + px] = acc[k] + bias[k];
