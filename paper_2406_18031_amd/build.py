@@ -24,20 +24,31 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-ffp
          "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+# Host-side undefined-behaviour checks for a check build: every check compiles to a trap
+# instruction in the host code (no sanitizer runtime to load, so the library still loads into
+# an ordinary Python process); device code is built as in the product library.
+UBSAN_FLAGS = ["-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fsanitize-trap=undefined",
+               "-Xarch_host", "-fno-sanitize-recover=all"]
+LIB_UBSAN = os.path.join(PKG, "libsflow_ubsan.so")
+
+
+def build(verbose: bool = False, ubsan: bool = False) -> str:
+    """Build libsflow.so; with ubsan=True the host-UB-trapping check build libsflow_ubsan.so
+    (loaded instead of the product library when SFLOW_LIB names it)."""
+    lib = LIB_UBSAN if ubsan else LIB
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, *(UBSAN_FLAGS if ubsan else []), *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libsflow.so")
+        raise RuntimeError(f"hipcc failed building {os.path.basename(lib)}")
     if verbose and r.stderr.strip():
         sys.stderr.write(r.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, ubsan="--ubsan" in sys.argv))

@@ -15,7 +15,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsflow.so")
+# SFLOW_LIB may name another build of the library to load (the host-UB-trapping check build
+# libsflow_ubsan.so, see build.py); by default the in-tree product library
+LIB_PATH = os.environ.get("SFLOW_LIB") or os.path.join(_PKG, "libsflow.so")
 
 SF_OK = 0
 SF_ERR_INVALID_ARG = -1
