@@ -50,5 +50,28 @@ def build(verbose: bool = False, ubsan: bool = False) -> str:
     return lib
 
 
+ASAN_DRIVER_SRC = os.path.join(ROOT, "tests", "host_asan", "abi_asan_driver.hip")
+ASAN_DRIVER = os.path.join(ROOT, "tests", "host_asan", "abi_asan_driver")
+
+
+def build_asan_driver(verbose: bool = False) -> str:
+    """The C ABI driver of tests/host_asan, built with the library's sources into one executable
+    whose host code runs under AddressSanitizer (its runtime linked in); device code as in the
+    product library."""
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    cmd = [HIPCC, *flags, "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+           "-fno-omit-frame-pointer", *SOURCES, ASAN_DRIVER_SRC, "-o", ASAN_DRIVER]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building the ABI driver")
+    return ASAN_DRIVER
+
+
 if __name__ == "__main__":
-    print(build(verbose=True, ubsan="--ubsan" in sys.argv))
+    if "--asan" in sys.argv:
+        print(build_asan_driver(verbose=True))
+    else:
+        print(build(verbose=True, ubsan="--ubsan" in sys.argv))
